@@ -1,0 +1,224 @@
+/*
+ * libcgdir -- contour-guided demons deformable registration (CG-DIR) on MI355X.
+ *
+ * Computes the deformation vector field u that registers a moving CT image I0 onto a
+ * target CT image T0 (section 2.1, Eq.1: u = argmin 1/2 |I0 o u - T0|^2 + a/2 |grad u|^2)
+ * with the contour term of Eq.2: each delineated structure i contributes a pair of
+ * modified images I_i = (1 + M_i/2) I0, T_i = (1 + N_i/2) T0 built from its mask on the
+ * moving image (M_i) and on the target image (N_i).  The iteration is Algorithm A:
+ * a multi-resolution pyramid, plain demons on the coarse levels, and at the finest level
+ * the loop {Eq.7 step du along n = grad I0~/|grad I0~| with beta = (T0 - I0~)^2,
+ * Gaussian smoothing of du, composite update u <- du + u o (Id + du), Gaussian
+ * smoothing of u} (section 2.2).  Arithmetic is FP32 on the GPU.
+ *
+ * Conventions (every entry point):
+ *   - volumes are float32, x fastest: element (i, j, l) at i + nx*(j + ny*l);
+ *   - a displacement field is float32 [3][nz][ny][nx]: the x, y, z components (SoA),
+ *     in voxel units, on the target grid, such that I0(x + u(x)) ~ T0(x);
+ *   - masks are uint8 [nz][ny][nx], 0 = outside, nonzero = inside;
+ *   - `where` says whether a buffer is host memory (CGDIR_HOST) or device memory on the
+ *     context's device (CGDIR_DEVICE);
+ *   - the caller owns every buffer it passes; the library owns only its context and the
+ *     sub-allocations it makes inside the pool the caller provides;
+ *   - every call returns CGDIR_OK (0) or a negative CGDIR_E_* code; no exception
+ *     crosses the boundary; cgdir_strerror() names a code.
+ */
+#ifndef CGDIR_H
+#define CGDIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGDIR_MAX_STRUCTS 8 /* structures per registration (bits of one mask byte) */
+#define CGDIR_MAX_LEVELS 6  /* pyramid levels */
+
+enum cgdir_code {
+    CGDIR_OK = 0,
+    CGDIR_E_INVAL = -1,     /* invalid argument (dims, k, pointers, parameters) */
+    CGDIR_E_NOMEM = -2,     /* the pool cannot hold the request */
+    CGDIR_E_HIP = -3,       /* a HIP runtime call failed */
+    CGDIR_E_BUSY = -4,      /* no free serving slot (only from non-queueing calls) */
+    CGDIR_E_NOTFOUND = -5,  /* unknown ticket */
+    CGDIR_E_CANCELLED = -6, /* the request was cancelled */
+    CGDIR_E_NONFINITE = -7, /* the field or the metric became NaN/Inf */
+    CGDIR_E_UNIMPL = -8,    /* a parameter combination that is not implemented */
+    CGDIR_E_TIMEOUT = -9    /* cgdir_wait timed out */
+};
+
+enum cgdir_where { CGDIR_HOST = 0, CGDIR_DEVICE = 1 };
+enum cgdir_warp_mode { CGDIR_WARP_LINEAR = 0, CGDIR_WARP_MASK = 1 };
+enum cgdir_state { CGDIR_QUEUED = 0, CGDIR_RUNNING = 1, CGDIR_DONE = 2, CGDIR_FAILED = 3,
+                   CGDIR_CANCELLED = 4 };
+enum cgdir_ctx_flags { CGDIR_CTX_PROFILE = 1 /* time every kernel launch with HIP events */ };
+
+typedef struct cgdir_ctx cgdir_ctx;
+
+/* Context description.  `stream` is a hipStream_t on `device` (NULL: the library creates
+ * one with default priority).  `pool`/`pool_bytes` is device memory the caller owns and
+ * keeps alive until cgdir_destroy returns (pool NULL: the library allocates pool_bytes
+ * itself at create time).  Every per-registration buffer is carved out of the pool, so
+ * no registration call allocates device memory.  `max_slots` bounds the registrations
+ * the serving loop runs concurrently (>= 1). */
+typedef struct cgdir_ctx_desc {
+    int device;
+    void *stream;
+    void *pool;
+    size_t pool_bytes;
+    int max_slots;
+    int flags;
+} cgdir_ctx_desc;
+
+/* A float32 volume (the moving or the target CT, HU). */
+typedef struct cgdir_volume {
+    const void *data;
+    int nx, ny, nz;
+    int where;
+} cgdir_volume;
+
+/* k structure masks on one image (section 2.1: O_i^p on the moving image, O_i^t on the
+ * target image; the i-th plane of both describes the same structure).  `planes` is a
+ * host array of k pointers, each to a uint8 volume of the image's dims. */
+typedef struct cgdir_masks {
+    int k;
+    const uint8_t *const *planes;
+    int where;
+} cgdir_masks;
+
+/* Parameters (section 2.2).  cgdir_params_default() fills the defaults named here. */
+typedef struct cgdir_params {
+    int levels;                      /* pyramid levels; default 1.  The paper uses 2 (section 2.2) */
+    int iters[CGDIR_MAX_LEVELS];     /* iterations per level, index 0 = finest; default 100 */
+    unsigned contour_level_mask;     /* bit l: contour terms at level l; default 1 (finest only,
+                                        Algorithm A); only bit 0 is supported */
+    float sigma_fluid;               /* Gaussian sigma smoothing du (voxels); default 1 */
+    float sigma_diff;                /* Gaussian sigma smoothing u (voxels); default 1 */
+    float restrict_sigma;            /* Gaussian sigma of the pyramid restriction; default 1 */
+    float lambda[CGDIR_MAX_STRUCTS]; /* contour weights; default 1e-3 (section 2.2) */
+    int sign[CGDIR_MAX_STRUCTS];     /* sign of M_i, N_i: +1 (structure brighter than its
+                                        surroundings) or -1; 0 = decide from the target image */
+    float intensity_offset;          /* c0: the modified images scale CT numbers HU + c0;
+                                        default 1000 */
+    int stop_mode;                   /* 0: run the iteration counts; 1: stopping rule of
+                                        section 2.2 at the finest level (see below) */
+    float stop_eps;                  /* default 1e-4 */
+    int stop_window;                 /* default 10 */
+    float norm_range;                /* delta = RMS over the UROI of (T0 - I0~)/norm_range;
+                                        default 2500 HU */
+    int uroi_margin[3];              /* UROI: target structures dilated by an ellipsoid with
+                                        these semi-axes (voxels); default {5, 5, 4} = 1 cm at
+                                        1.97 x 1.97 x 2.5 mm voxels */
+    const float *initial_dvf;        /* optional [3][nz][ny][nx] field to start the finest level
+                                        from; then levels must be 1 (section 4: warm start) */
+    int initial_dvf_where;
+    double *delta_hist;              /* optional host output: delta at each finest-level
+                                        iteration (capacity iters[0]) */
+    int *iters_done;                 /* optional host output: finest-level iterations run */
+} cgdir_params;
+
+/* Stopping rule (section 2.2, delta = RMS intensity difference over the UROI, l = change of
+ * delta): the finest level stops after iteration n when (n + 1) is a multiple of
+ * stop_window, n >= stop_window and delta_{n - stop_window} - delta_n <= stop_eps. */
+
+void cgdir_params_default(cgdir_params *p);
+
+/* Create a context on desc->device.  Returns CGDIR_E_INVAL for a bad description,
+ * CGDIR_E_HIP if the device cannot be used, CGDIR_E_NOMEM if pool is NULL and
+ * pool_bytes cannot be allocated. */
+int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc);
+
+/* Cancel queued requests, wait for running ones, release the context (not the pool). */
+int cgdir_destroy(cgdir_ctx *ctx);
+
+/* Register one pair, blocking (Algorithm A).  target and moving have the same dims
+ * (each >= 1, at most 4096).  target_masks and moving_masks have the same k
+ * (0 <= k <= CGDIR_MAX_STRUCTS; k = 0 is plain demons) and the image's dims; may be NULL
+ * for k = 0.  dvf_out receives u, [3][nz][ny][nx] float32 at dvf_where.
+ * Returns after dvf_out is written.  Inputs are read in place when on the device.
+ * Errors: CGDIR_E_INVAL (dims, k, pointers, parameters), CGDIR_E_NOMEM (the pool cannot
+ * hold cgdir_footprint() bytes), CGDIR_E_NONFINITE (non-finite inputs produced a
+ * non-finite field), CGDIR_E_HIP. */
+int cgdir_register(cgdir_ctx *ctx, const cgdir_volume *target, const cgdir_volume *moving,
+                   const cgdir_masks *target_masks, const cgdir_masks *moving_masks,
+                   const cgdir_params *params, float *dvf_out, int dvf_where);
+
+/* Warp src with a field on src's grid: out(x) = src(x + dvf(x)), trilinear, sample
+ * position clamped to the volume (the interpolation of section 2.2, kernel 4).
+ * CGDIR_WARP_LINEAR: src and out float32.  CGDIR_WARP_MASK: src and out uint8; the
+ * trilinear value of the 0/1 mask, inside when >= 0.5 (propagation of a structure,
+ * section 2.3).  dvf and out have src->where's placement.  Blocking. */
+int cgdir_warp(cgdir_ctx *ctx, const cgdir_volume *src, const float *dvf, int mode, void *out);
+
+/* One registration request for the batched and served paths: the arguments of
+ * cgdir_register.  Every buffer must stay valid and unmodified until the request
+ * reaches a final state; the library does not copy them at submit. */
+typedef struct cgdir_request {
+    cgdir_volume target;
+    cgdir_volume moving;
+    cgdir_masks target_masks;
+    cgdir_masks moving_masks;
+    cgdir_params params;
+    float *dvf_out;
+    int dvf_where;
+} cgdir_request;
+
+/* Register n pairs of uneven sizes and structure counts together on the device
+ * (blocking): every iteration phase runs once for all pairs that still have work.
+ * Each pair's result equals what cgdir_register returns for it alone.  status (host,
+ * n entries, may be NULL) receives each pair's code.  Returns the first failing code.
+ * Errors: as cgdir_register; CGDIR_E_NOMEM when the pool cannot hold all pairs at once. */
+int cgdir_register_batch(cgdir_ctx *ctx, int n, const cgdir_request *reqs, int *status);
+
+/* Serving: queue a request, non-blocking.  Requests are admitted in arrival order when a
+ * slot is free and the pool holds their footprint; admitted requests advance together,
+ * iteration by iteration, and new ones join between iterations (continuous batching).
+ * Returns CGDIR_E_NOMEM at once if the footprint exceeds the whole pool, CGDIR_E_INVAL
+ * for invalid arguments.  *ticket identifies the request. */
+int cgdir_submit(cgdir_ctx *ctx, const cgdir_request *req, uint64_t *ticket);
+
+typedef struct cgdir_status {
+    int state;           /* enum cgdir_state */
+    int error;           /* final code when DONE / FAILED / CANCELLED */
+    int level;           /* current pyramid level */
+    int iter;            /* iterations done at that level */
+    double last_delta;   /* latest delta (when computed) */
+    int64_t t_submit_ns; /* steady-clock timestamps */
+    int64_t t_admit_ns;
+    int64_t t_done_ns;
+} cgdir_status;
+
+/* Non-blocking status of a ticket.  CGDIR_E_NOTFOUND for an unknown ticket. */
+int cgdir_poll(cgdir_ctx *ctx, uint64_t ticket, cgdir_status *st);
+
+/* Cancel a queued request (a running one finishes).  CGDIR_E_NOTFOUND, or CGDIR_E_BUSY
+ * when it is already running or finished. */
+int cgdir_cancel(cgdir_ctx *ctx, uint64_t ticket);
+
+/* Wait until the request is final or timeout_ns elapses (< 0: forever).
+ * Returns the request's final code, CGDIR_E_TIMEOUT or CGDIR_E_NOTFOUND. */
+int cgdir_wait(cgdir_ctx *ctx, uint64_t ticket, int64_t timeout_ns);
+
+/* Pool bytes one registration of this size reserves (admission uses it). */
+size_t cgdir_footprint(int nx, int ny, int nz, int k, const cgdir_params *params);
+
+/* Static name of a code. */
+const char *cgdir_strerror(int code);
+
+/* Per-kernel timing, filled when the context was created with CGDIR_CTX_PROFILE:
+ * launches and summed duration (HIP events on the context stream) of each kernel since
+ * the last reset.  Returns the number of entries written (<= cap). */
+typedef struct cgdir_kernel_stat {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+    double voxels;       /* voxels processed by those launches */
+} cgdir_kernel_stat;
+int cgdir_kernel_stats(cgdir_ctx *ctx, cgdir_kernel_stat *out, int cap, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libcgdir.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cgdir {
+
+constexpr int kMaxStructs = 8;
+constexpr int kMaxRadius = 6;       // Gaussian radius ceil(3 sigma) <= 6  (sigma <= 2)
+constexpr int kTileX = 64;          // one wavefront spans a tile row
+constexpr int kMaxUroiMargin = 8;
+
+// Geometry of one volume.
+struct Dims {
+    int nx, ny, nz;
+    __host__ __device__ int64_t n() const { return (int64_t)nx * ny * nz; }
+};
+
+// Arguments of the fused force kernel: warp of I0 (and of the masked images m_i (I0 + c0)),
+// central differences, Eq.7, optional stopping-metric partials.
+struct ForceArgs {
+    const float *I0;          // moving image at this level
+    const float *T0;          // target image at this level
+    const uint8_t *mbits;     // bit i = voxel inside structure i on the moving image (or null)
+    const uint8_t *tbits;     // same on the target image (or null)
+    const uint8_t *uroi;      // stopping region (or null: no metric)
+    const float *u[3];        // current field
+    float *du[3];             // output step
+    float *partials;          // per-block sums of ((T0 - I0~)/norm)^2 over the UROI
+    Dims d;
+    int k;                    // active structures (<= kMaxStructs)
+    float lam[kMaxStructs];   // lambda_i
+    float hs[kMaxStructs];    // s_i / 2
+    float c0;                 // CT-number offset
+    float inv_norm;           // 1 / norm_range
+    int tz;                   // planes per block (z chunk)
+};
+
+// Arguments of the separable Gaussian kernels.
+struct SmoothArgs {
+    const float *in[3];
+    const float *u[3];        // compose mode: the field gathered at x + smoothed(in)
+    float *out[3];
+    Dims d;
+    float w[kMaxRadius + 1];  // w[0] centre, w[m] = weight at +-m
+    int tz;
+};
+
+// ---- launchers (cgdir_kernels.hip); each returns the hipError_t of its launch -------
+hipError_t launch_force(const ForceArgs &a, int kp, int ty, hipStream_t s, int *blocks_out);
+hipError_t launch_smooth(const SmoothArgs &a, int radius, bool compose, int ty, hipStream_t s);
+hipError_t launch_delta_finalize(const float *partials, int nblocks, const int64_t *count,
+                                 double *out, float inv_dummy, hipStream_t s);
+hipError_t launch_restrict_pass(const float *in, float *out, Dims din, int axis, const float *w,
+                                int radius, hipStream_t s);
+hipError_t launch_prolong(const float *const uc[3], Dims dc, float *const uf[3], Dims df,
+                          hipStream_t s);
+hipError_t launch_pack_masks(const uint8_t *const *planes, int k, int64_t n, uint8_t *bits,
+                             hipStream_t s);
+hipError_t launch_uroi(const uint8_t *tbits, Dims d, const int margin[3], uint8_t *rowdist,
+                       uint8_t *uroi, hipStream_t s);
+hipError_t launch_count(const uint8_t *m, int64_t n, uint8_t bitmask, int64_t *partials,
+                        int *nparts, int64_t *out, hipStream_t s);
+hipError_t launch_warp_linear(const float *src, Dims d, const float *const u[3], float *out,
+                              hipStream_t s);
+hipError_t launch_warp_mask(const uint8_t *src, Dims d, const float *const u[3], uint8_t *out,
+                            hipStream_t s);
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_nonfinite(const float *p, int64_t n, int *flag, hipStream_t s);
+hipError_t launch_sign_stats(const float *T0, const uint8_t *tbits, const uint8_t *dil, int bit,
+                             int64_t n, double *partials, int *nparts, double *out4,
+                             hipStream_t s);
+hipError_t launch_dilate_bit(const uint8_t *bits, int bit, Dims d, const int margin[3],
+                             uint8_t *rowdist, uint8_t *out, hipStream_t s);
+
+int force_partial_blocks(Dims d, int ty, int tz);
+
+}  // namespace cgdir

@@ -1,0 +1,1185 @@
+// Host runtime of libcgdir: pool sub-allocator, registration driver (Algorithm A:
+// pyramid, coarse demons, finest-level CG-DIR loop, stopping rule), batched execution,
+// the serving scheduler, and the C-ABI of include/cgdir.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "cgdir.h"
+#include "cgdir_internal.h"
+
+namespace cgdir {
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ------------------------------------------------------------------ pool sub-allocator
+// First-fit over one device buffer; every registration buffer comes from here.
+class Pool {
+  public:
+    void init(char *base, size_t bytes)
+    {
+        base_ = base;
+        size_ = bytes;
+        free_.clear();
+        used_.clear();
+        if (bytes) free_[0] = bytes;
+    }
+    void *alloc(size_t bytes)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        bytes = align_up(bytes ? bytes : 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                size_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > bytes) free_[off + bytes] = sz - bytes;
+                used_[off] = bytes;
+                in_use_ += bytes;
+                return base_ + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(void *p)
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> g(mu_);
+        size_t off = (char *)p - base_;
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t sz = u->second;
+        used_.erase(u);
+        in_use_ -= sz;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + sz == nx->first) {  // merge with the next block
+            sz += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {  // merge with the previous block
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += sz;
+                return;
+            }
+        }
+        free_[off] = sz;
+    }
+    size_t size() const { return size_; }
+    size_t in_use()
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        return in_use_;
+    }
+
+  private:
+    std::mutex mu_;
+    char *base_ = nullptr;
+    size_t size_ = 0;
+    size_t in_use_ = 0;
+    std::map<size_t, size_t> free_;
+    std::unordered_map<size_t, size_t> used_;
+};
+
+// ------------------------------------------------------------------ derived parameters
+
+int gauss_radius(float sigma) { return sigma > 0.f ? (int)std::ceil(3.0 * (double)sigma) : 0; }
+
+// sampled Gaussian of radius ceil(3 sigma), normalised to sum 1 (computed in double)
+void gauss_taps(float sigma, float *w)
+{
+    const int R = gauss_radius(sigma);
+    for (int m = 0; m <= kMaxRadius; ++m) w[m] = 0.f;
+    if (R == 0) {
+        w[0] = 1.f;
+        return;
+    }
+    double t[kMaxRadius + 1], sum = 0.0;
+    for (int m = 0; m <= R; ++m) {
+        t[m] = std::exp(-(double)(m * m) / (2.0 * (double)sigma * (double)sigma));
+        sum += m == 0 ? t[m] : 2.0 * t[m];
+    }
+    for (int m = 0; m <= R; ++m) w[m] = (float)(t[m] / sum);
+}
+
+int kp_for(int k) { return k == 0 ? 0 : (k == 1 ? 1 : (k == 2 ? 2 : (k <= 4 ? 4 : 8))); }
+
+Dims level_dims(Dims d0, int l)
+{
+    Dims d = d0;
+    for (int i = 0; i < l; ++i) {
+        d.nx = (d.nx + 1) / 2;
+        d.ny = (d.ny + 1) / 2;
+        d.nz = (d.nz + 1) / 2;
+    }
+    return d;
+}
+
+// launch geometry (tile rows, z planes per block) of the iteration kernels
+struct Tuning {
+    int force_ty = 4, force_tz = 16;
+    int smooth_ty = 8, smooth_tz = 32;
+};
+
+bool want_delta(const cgdir_params &p) { return p.stop_mode != 0 || p.delta_hist != nullptr; }
+
+size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, const Tuning &t)
+{
+    const size_t n0 = (size_t)d0.n();
+    size_t b = 0;
+    b += 3 * align_up(3 * n0 * sizeof(float));  // u, du, uc
+    for (int l = 1; l < p.levels; ++l) b += 2 * align_up((size_t)level_dims(d0, l).n() * sizeof(float));
+    if (host_images) b += 2 * align_up(n0 * sizeof(float));
+    if (k > 0) b += 2 * align_up(n0);  // bit-planes
+    if (want_delta(p)) {
+        b += align_up(n0);  // UROI
+        b += align_up((size_t)force_partial_blocks(d0, t.force_ty, t.force_tz) * sizeof(float));
+        b += align_up((size_t)std::max(p.iters[0], 1) * sizeof(double));
+    }
+    b += align_up(8192);  // counters, flags, reduction partials
+    return b;
+}
+
+// ------------------------------------------------------------------ profiling
+
+enum KernelId { K_FORCE, K_SMOOTH_COMPOSE, K_SMOOTH, K_DELTA, K_RESTRICT, K_PROLONG, K_PACK, K_UROI,
+                K_WARP, K_MISC, K_COUNT };
+const char *kKernelNames[K_COUNT] = {"force", "smooth_compose", "smooth", "delta", "restrict",
+                                     "prolong", "pack_masks", "uroi", "warp", "misc"};
+
+}  // namespace
+}  // namespace cgdir
+
+using namespace cgdir;
+
+struct Job;
+
+struct cgdir_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *own_pool = nullptr;
+    Pool pool;
+    int max_slots = 1;
+    bool profile = false;
+    Tuning tune;
+
+    // profiling
+    std::mutex prof_mu;
+    struct Pending {
+        int id;
+        hipEvent_t a, b;
+        double voxels;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare_events;
+    int64_t launches[K_COUNT] = {};
+    double total_ms[K_COUNT] = {};
+    double voxels[K_COUNT] = {};
+
+    // serving
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread sched;
+    bool sched_started = false;
+    bool stopping = false;
+    uint64_t next_ticket = 1;
+    std::deque<uint64_t> queue;
+    struct Request;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::mutex launch_mu;  // keeps each job's launch sequence contiguous on the stream
+};
+
+namespace cgdir {
+namespace {
+
+hipEvent_t take_event(cgdir_ctx *c)
+{
+    if (!c->spare_events.empty()) {
+        hipEvent_t e = c->spare_events.back();
+        c->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void drain_profile(cgdir_ctx *c)  // caller holds prof_mu
+{
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->launches[p.id] += 1;
+            c->total_ms[p.id] += ms;
+            c->voxels[p.id] += p.voxels;
+        }
+        c->spare_events.push_back(p.a);
+        c->spare_events.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
+// Runs `fn` (one kernel launch) on the context stream, bracketed by events when profiling.
+template <typename F>
+hipError_t timed(cgdir_ctx *c, int id, double vox, F &&fn)
+{
+    if (!c->profile) return fn();
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    if (c->pending.size() > 8192) drain_profile(c);
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) return fn();
+    hipEventRecord(a, c->stream);
+    hipError_t e = fn();
+    hipEventRecord(b, c->stream);
+    c->pending.push_back({id, a, b, vox});
+    return e;
+}
+
+int hip_code(hipError_t e) { return e == hipSuccess ? CGDIR_OK : CGDIR_E_HIP; }
+
+#define CG_TRY(expr)                          \
+    do {                                      \
+        int _rc = (expr);                     \
+        if (_rc != CGDIR_OK) return _rc;      \
+    } while (0)
+#define HIP_TRY(expr)                         \
+    do {                                      \
+        if ((expr) != hipSuccess) return CGDIR_E_HIP; \
+    } while (0)
+
+// ------------------------------------------------------------------ validation
+
+int check_volume(const cgdir_volume *v)
+{
+    if (!v || !v->data) return CGDIR_E_INVAL;
+    if (v->where != CGDIR_HOST && v->where != CGDIR_DEVICE) return CGDIR_E_INVAL;
+    if (v->nx < 1 || v->ny < 1 || v->nz < 1 || v->nx > 4096 || v->ny > 4096 || v->nz > 4096)
+        return CGDIR_E_INVAL;
+    if ((int64_t)v->nx * v->ny * v->nz > (int64_t(1) << 30)) return CGDIR_E_INVAL;
+    return CGDIR_OK;
+}
+
+int check_params(const cgdir_params &p, int k)
+{
+    if (p.levels < 1 || p.levels > CGDIR_MAX_LEVELS) return CGDIR_E_INVAL;
+    for (int l = 0; l < p.levels; ++l)
+        if (p.iters[l] < 0) return CGDIR_E_INVAL;
+    if (p.contour_level_mask > 1u) return CGDIR_E_UNIMPL;
+    const float sig[3] = {p.sigma_fluid, p.sigma_diff, p.restrict_sigma};
+    for (float s : sig)
+        if (!(s >= 0.f) || gauss_radius(s) > kMaxRadius) return CGDIR_E_INVAL;
+    for (int i = 0; i < k; ++i) {
+        if (!(p.lambda[i] >= 0.f) || !std::isfinite(p.lambda[i])) return CGDIR_E_INVAL;
+        if (p.sign[i] < -1 || p.sign[i] > 1) return CGDIR_E_INVAL;
+    }
+    if (!std::isfinite(p.intensity_offset)) return CGDIR_E_INVAL;
+    if (p.stop_mode != 0 && p.stop_mode != 1) return CGDIR_E_INVAL;
+    if (p.stop_window < 1 || !(p.norm_range > 0.f)) return CGDIR_E_INVAL;
+    for (int a = 0; a < 3; ++a)
+        if (p.uroi_margin[a] < 0 || p.uroi_margin[a] > kMaxUroiMargin) return CGDIR_E_INVAL;
+    if (p.initial_dvf) {
+        if (p.levels != 1) return CGDIR_E_INVAL;
+        if (p.initial_dvf_where != CGDIR_HOST && p.initial_dvf_where != CGDIR_DEVICE) return CGDIR_E_INVAL;
+    }
+    return CGDIR_OK;
+}
+
+int check_masks(const cgdir_masks *m, int *k)
+{
+    if (!m) {
+        *k = 0;
+        return CGDIR_OK;
+    }
+    if (m->k < 0 || m->k > CGDIR_MAX_STRUCTS) return CGDIR_E_INVAL;
+    if (m->k > 0) {
+        if (!m->planes || (m->where != CGDIR_HOST && m->where != CGDIR_DEVICE)) return CGDIR_E_INVAL;
+        for (int i = 0; i < m->k; ++i)
+            if (!m->planes[i]) return CGDIR_E_INVAL;
+    }
+    *k = m->k;
+    return CGDIR_OK;
+}
+
+int check_request(const cgdir_request &r)
+{
+    CG_TRY(check_volume(&r.target));
+    CG_TRY(check_volume(&r.moving));
+    if (r.target.nx != r.moving.nx || r.target.ny != r.moving.ny || r.target.nz != r.moving.nz)
+        return CGDIR_E_INVAL;
+    int kt = 0, km = 0;
+    CG_TRY(check_masks(&r.target_masks, &kt));
+    CG_TRY(check_masks(&r.moving_masks, &km));
+    if (kt != km) return CGDIR_E_INVAL;
+    CG_TRY(check_params(r.params, kt));
+    if (!r.dvf_out || (r.dvf_where != CGDIR_HOST && r.dvf_where != CGDIR_DEVICE)) return CGDIR_E_INVAL;
+    return CGDIR_OK;
+}
+
+}  // namespace
+}  // namespace cgdir
+
+// ------------------------------------------------------------------ one registration
+
+struct Job {
+    cgdir_ctx *ctx = nullptr;
+    cgdir_request req{};
+    const uint8_t *tplanes[CGDIR_MAX_STRUCTS] = {};
+    const uint8_t *mplanes[CGDIR_MAX_STRUCTS] = {};
+    int k = 0;
+    int L = 1;
+    Dims d0{};
+    bool host_images = false;
+    bool delta_on = false;
+    float lam[kMaxStructs] = {}, hs[kMaxStructs] = {};
+    int sign[kMaxStructs] = {};
+    float wf[kMaxRadius + 1], wd[kMaxRadius + 1], wr[kMaxRadius + 1];
+    int Rf = 0, Rd = 0, Rr = 0;
+
+    std::vector<void *> allocs;
+    const float *I0[CGDIR_MAX_LEVELS] = {}, *T0[CGDIR_MAX_LEVELS] = {};
+    uint8_t *mbits = nullptr, *tbits = nullptr, *uroi = nullptr;
+    float *ubuf = nullptr, *dubuf = nullptr, *ucbuf = nullptr;
+    float *partials = nullptr;
+    double *delta_dev = nullptr;
+    int64_t *misc_i64 = nullptr;  // [0] UROI count, [1..] reduction partials
+    double *misc_f64 = nullptr;
+    int *flag = nullptr;
+    double *sign_parts = nullptr;
+
+    // progress
+    int level = 0;      // current level (coarsest first)
+    int iter = 0;       // iterations done at the current level
+    bool level_started = false;
+    bool finished = false;
+    int iters_done0 = 0;
+    std::vector<double> delta_host;
+
+    size_t need() const { return footprint_bytes(d0, k, req.params, host_images, ctx->tune); }
+
+    int init(cgdir_ctx *c, const cgdir_request &r)
+    {
+        ctx = c;
+        CG_TRY(check_request(r));
+        req = r;
+        k = r.target_masks.k;
+        if (r.moving_masks.k != k) return CGDIR_E_INVAL;
+        for (int i = 0; i < k; ++i) {
+            tplanes[i] = r.target_masks.planes[i];
+            mplanes[i] = r.moving_masks.planes[i];
+        }
+        req.target_masks.planes = tplanes;
+        req.moving_masks.planes = mplanes;
+        d0 = Dims{r.target.nx, r.target.ny, r.target.nz};
+        L = r.params.levels;
+        host_images = r.target.where == CGDIR_HOST || r.moving.where == CGDIR_HOST;
+        delta_on = want_delta(r.params);
+        for (int i = 0; i < k; ++i) {
+            lam[i] = r.params.lambda[i];
+            sign[i] = r.params.sign[i];
+        }
+        gauss_taps(r.params.sigma_fluid, wf);
+        gauss_taps(r.params.sigma_diff, wd);
+        gauss_taps(r.params.restrict_sigma, wr);
+        Rf = gauss_radius(r.params.sigma_fluid);
+        Rd = gauss_radius(r.params.sigma_diff);
+        Rr = gauss_radius(r.params.restrict_sigma);
+        level = L - 1;
+        iter = 0;
+        return CGDIR_OK;
+    }
+
+    void *take(size_t bytes)
+    {
+        void *p = ctx->pool.alloc(bytes);
+        if (p) allocs.push_back(p);
+        return p;
+    }
+
+    void release()
+    {
+        for (void *p : allocs) ctx->pool.release(p);
+        allocs.clear();
+    }
+
+    int allocate()
+    {
+        const size_t n0 = (size_t)d0.n();
+        ubuf = (float *)take(3 * n0 * sizeof(float));
+        dubuf = (float *)take(3 * n0 * sizeof(float));
+        ucbuf = (float *)take(3 * n0 * sizeof(float));
+        bool ok = ubuf && dubuf && ucbuf;
+        if (host_images) {
+            float *a = (float *)take(n0 * sizeof(float));
+            float *b = (float *)take(n0 * sizeof(float));
+            I0[0] = a;
+            T0[0] = b;
+            ok = ok && a && b;
+        } else {
+            I0[0] = (const float *)req.moving.data;
+            T0[0] = (const float *)req.target.data;
+        }
+        for (int l = 1; l < L; ++l) {
+            const size_t nl = (size_t)level_dims(d0, l).n();
+            float *a = (float *)take(nl * sizeof(float));
+            float *b = (float *)take(nl * sizeof(float));
+            I0[l] = a;
+            T0[l] = b;
+            ok = ok && a && b;
+        }
+        if (k > 0) {
+            mbits = (uint8_t *)take(n0);
+            tbits = (uint8_t *)take(n0);
+            ok = ok && mbits && tbits;
+        }
+        if (delta_on) {
+            uroi = (uint8_t *)take(n0);
+            partials = (float *)take((size_t)force_partial_blocks(d0, ctx->tune.force_ty, ctx->tune.force_tz) *
+                                     sizeof(float));
+            delta_dev = (double *)take((size_t)std::max(req.params.iters[0], 1) * sizeof(double));
+            ok = ok && uroi && partials && delta_dev;
+        }
+        char *misc = (char *)take(8192);
+        ok = ok && misc;
+        if (!ok) {
+            release();
+            return CGDIR_E_NOMEM;
+        }
+        misc_i64 = (int64_t *)misc;               // [0] count, [8, 264) count partials
+        misc_f64 = (double *)(misc + 2304);        // 4 doubles
+        flag = (int *)(misc + 2304 + 64);
+        sign_parts = (double *)(misc + 4096);      // 128 x 4 doubles
+        return CGDIR_OK;
+    }
+
+    float *comp(float *base, int c) const { return base + (size_t)c * (size_t)d0.n(); }
+
+    // device setup: copies, mask bits, UROI, signs, pyramid, initial field
+    int setup()
+    {
+        hipStream_t s = ctx->stream;
+        const int64_t n0 = d0.n();
+        if (host_images) {
+            const hipMemcpyKind km = req.moving.where == CGDIR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+            const hipMemcpyKind kt = req.target.where == CGDIR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+            HIP_TRY(hipMemcpyAsync((void *)I0[0], req.moving.data, n0 * sizeof(float), km, s));
+            HIP_TRY(hipMemcpyAsync((void *)T0[0], req.target.data, n0 * sizeof(float), kt, s));
+        }
+        if (k > 0) {
+            for (int side = 0; side < 2; ++side) {
+                const cgdir_masks &m = side == 0 ? req.moving_masks : req.target_masks;
+                uint8_t *bits = side == 0 ? mbits : tbits;
+                const uint8_t *planes[kMaxStructs];
+                if (m.where == CGDIR_HOST) {  // stage through the (still unused) uc buffer
+                    uint8_t *stage = (uint8_t *)ucbuf;
+                    for (int i = 0; i < k; ++i) {
+                        HIP_TRY(hipMemcpyAsync(stage + (size_t)i * n0, m.planes[i], n0, hipMemcpyHostToDevice, s));
+                        planes[i] = stage + (size_t)i * n0;
+                    }
+                } else {
+                    for (int i = 0; i < k; ++i) planes[i] = m.planes[i];
+                }
+                HIP_TRY(timed(ctx, K_PACK, (double)n0, [&] { return launch_pack_masks(planes, k, n0, bits, s); }));
+                if (m.where == CGDIR_HOST) HIP_TRY(hipStreamSynchronize(s));  // staging reused next side
+            }
+        }
+        uint8_t *rowdist = (uint8_t *)dubuf;  // scratch during setup
+        if (delta_on) {
+            if (k > 0) {
+                HIP_TRY(timed(ctx, K_UROI, (double)n0,
+                              [&] { return launch_uroi(tbits, d0, req.params.uroi_margin, rowdist, uroi, s); }));
+            } else {
+                HIP_TRY(hipMemsetAsync(uroi, 1, n0, s));
+            }
+            int np = 0;
+            HIP_TRY(launch_count(uroi, n0, 0xFF, misc_i64 + 8, &np, misc_i64, s));
+        }
+        bool need_auto = false;
+        for (int i = 0; i < k; ++i) need_auto |= sign[i] == 0;
+        if (need_auto) {
+            uint8_t *dil = (uint8_t *)ucbuf;
+            double *parts = sign_parts;
+            for (int i = 0; i < k; ++i) {
+                if (sign[i] != 0) continue;
+                HIP_TRY(launch_dilate_bit(tbits, i, d0, req.params.uroi_margin, rowdist, dil, s));
+                int np = 0;
+                HIP_TRY(launch_sign_stats(T0[0], tbits, dil, i, n0, parts, &np, misc_f64, s));
+                double h[4];
+                HIP_TRY(hipMemcpyAsync(h, misc_f64, sizeof(h), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                sign[i] = (h[1] == 0.0 || h[3] == 0.0) ? 1 : (h[0] / h[1] >= h[2] / h[3] ? 1 : -1);
+            }
+        }
+        for (int i = 0; i < k; ++i) hs[i] = 0.5f * (float)sign[i];
+        // pyramid: R(F)(j) = (G * F)(2j), one axis at a time through two scratch volumes
+        for (int l = 1; l < L; ++l) {
+            const Dims din = level_dims(d0, l - 1);
+            Dims dx = din;
+            dx.nx = (din.nx + 1) / 2;
+            Dims dy = dx;
+            dy.ny = (dx.ny + 1) / 2;
+            float *t1 = dubuf;                   // <= n0 floats
+            float *t2 = dubuf + (size_t)n0;      // <= n0 floats
+            for (int img = 0; img < 2; ++img) {
+                const float *src = img == 0 ? I0[l - 1] : T0[l - 1];
+                float *dst = (float *)(img == 0 ? I0[l] : T0[l]);
+                HIP_TRY(timed(ctx, K_RESTRICT, (double)din.n(), [&] {
+                    hipError_t e = launch_restrict_pass(src, t1, din, 0, wr, Rr, s);
+                    if (e == hipSuccess) e = launch_restrict_pass(t1, t2, dx, 1, wr, Rr, s);
+                    if (e == hipSuccess) e = launch_restrict_pass(t2, dst, dy, 2, wr, Rr, s);
+                    return e;
+                }));
+            }
+        }
+        // u0 := 0 at the coarsest level, or the given field at the finest
+        if (req.params.initial_dvf) {
+            const hipMemcpyKind kd = req.params.initial_dvf_where == CGDIR_HOST ? hipMemcpyHostToDevice
+                                                                                : hipMemcpyDeviceToDevice;
+            HIP_TRY(hipMemcpyAsync(ubuf, req.params.initial_dvf, 3 * n0 * sizeof(float), kd, s));
+        } else {
+            HIP_TRY(launch_fill(ubuf, 3 * n0, 0.f, s));
+        }
+        HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+        return CGDIR_OK;
+    }
+
+    bool contour_at(int l) const { return k > 0 && ((req.params.contour_level_mask >> l) & 1u); }
+
+    // prolongation into the next finer level (nothing at the coarsest)
+    int begin_level()
+    {
+        level_started = true;
+        if (level == L - 1) return CGDIR_OK;
+        const Dims dc = level_dims(d0, level + 1), df = level_dims(d0, level);
+        const float *uc[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
+        float *uf[3] = {comp(dubuf, 0), comp(dubuf, 1), comp(dubuf, 2)};
+        HIP_TRY(timed(ctx, K_PROLONG, (double)df.n(), [&] { return launch_prolong(uc, dc, uf, df, ctx->stream); }));
+        std::swap(ubuf, dubuf);
+        return CGDIR_OK;
+    }
+
+    // one iteration of the loop at the current level
+    int iterate()
+    {
+        hipStream_t s = ctx->stream;
+        const Dims d = level_dims(d0, level);
+        const bool contour = contour_at(level);
+        const bool metric = delta_on && level == 0;
+        ForceArgs fa{};
+        fa.I0 = I0[level];
+        fa.T0 = T0[level];
+        fa.mbits = contour ? mbits : nullptr;
+        fa.tbits = contour ? tbits : nullptr;
+        fa.uroi = metric ? uroi : nullptr;
+        fa.partials = metric ? partials : nullptr;
+        for (int c = 0; c < 3; ++c) {
+            fa.u[c] = comp(ubuf, c);
+            fa.du[c] = comp(dubuf, c);
+        }
+        fa.d = d;
+        fa.k = contour ? k : 0;
+        for (int i = 0; i < kMaxStructs; ++i) {
+            fa.lam[i] = i < k ? lam[i] : 0.f;
+            fa.hs[i] = i < k ? hs[i] : 0.f;
+        }
+        fa.c0 = req.params.intensity_offset;
+        fa.inv_norm = 1.0f / req.params.norm_range;
+        fa.tz = ctx->tune.force_tz;
+        int nblocks = 0;
+        const int kp = kp_for(fa.k);
+        HIP_TRY(timed(ctx, K_FORCE, (double)d.n(), [&] { return launch_force(fa, kp, ctx->tune.force_ty, s, &nblocks); }));
+        if (metric)
+            HIP_TRY(timed(ctx, K_DELTA, 0.0, [&] {
+                return launch_delta_finalize(partials, nblocks, misc_i64, delta_dev + iter, 0.f, s);
+            }));
+        SmoothArgs sa{};
+        for (int c = 0; c < 3; ++c) {
+            sa.in[c] = comp(dubuf, c);
+            sa.u[c] = comp(ubuf, c);
+            sa.out[c] = comp(ucbuf, c);
+        }
+        sa.d = d;
+        sa.tz = ctx->tune.smooth_tz;
+        for (int m = 0; m <= kMaxRadius; ++m) sa.w[m] = wf[m];
+        HIP_TRY(timed(ctx, K_SMOOTH_COMPOSE, (double)d.n(),
+                      [&] { return launch_smooth(sa, Rf, true, ctx->tune.smooth_ty, s); }));
+        SmoothArgs sb{};
+        for (int c = 0; c < 3; ++c) {
+            sb.in[c] = comp(ucbuf, c);
+            sb.u[c] = nullptr;
+            sb.out[c] = comp(ubuf, c);
+        }
+        sb.d = d;
+        sb.tz = ctx->tune.smooth_tz;
+        for (int m = 0; m <= kMaxRadius; ++m) sb.w[m] = wd[m];
+        HIP_TRY(timed(ctx, K_SMOOTH, (double)d.n(), [&] { return launch_smooth(sb, Rd, false, ctx->tune.smooth_ty, s); }));
+        ++iter;
+        return CGDIR_OK;
+    }
+
+    int end_level()
+    {
+        const Dims d = level_dims(d0, level);
+        for (int c = 0; c < 3; ++c) HIP_TRY(launch_nonfinite(comp(ubuf, c), d.n(), flag, ctx->stream));
+        return CGDIR_OK;
+    }
+
+    // stopping rule at the finest level after iteration n = iter - 1
+    bool stop_due(const std::vector<double> &h) const
+    {
+        const int W = req.params.stop_window;
+        const int n = iter - 1;
+        return req.params.stop_mode && level == 0 && (n + 1) % W == 0 && n - W >= 0 &&
+               h[n - W] - h[n] <= (double)req.params.stop_eps;
+    }
+
+    // advance by at most `budget` iterations; returns CGDIR_OK, sets `finished`
+    int advance(int budget, bool allow_sync)
+    {
+        while (budget > 0 && !finished) {
+            if (!level_started) CG_TRY(begin_level());
+            const int total = req.params.iters[level];
+            bool stop = false;
+            if (iter < total) {
+                CG_TRY(iterate());
+                --budget;
+                if (req.params.stop_mode && level == 0 && iter % req.params.stop_window == 0 && allow_sync) {
+                    delta_host.resize(iter);
+                    HIP_TRY(hipMemcpyAsync(delta_host.data(), delta_dev, iter * sizeof(double), hipMemcpyDeviceToHost,
+                                           ctx->stream));
+                    HIP_TRY(hipStreamSynchronize(ctx->stream));
+                    stop = stop_due(delta_host);
+                }
+            }
+            if (iter >= total || stop) {
+                CG_TRY(end_level());
+                if (level == 0) {
+                    iters_done0 = iter;
+                    finished = true;
+                } else {
+                    --level;
+                    iter = 0;
+                    level_started = false;
+                }
+            }
+        }
+        return CGDIR_OK;
+    }
+
+    // copy the result out (asynchronous on the stream)
+    int emit()
+    {
+        const int64_t n0 = d0.n();
+        const hipMemcpyKind kd = req.dvf_where == CGDIR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        HIP_TRY(hipMemcpyAsync(req.dvf_out, ubuf, 3 * n0 * sizeof(float), kd, ctx->stream));
+        return CGDIR_OK;
+    }
+
+    // after the stream has drained: host-side outputs and the non-finite check
+    int conclude()
+    {
+        if (delta_on && req.params.delta_hist && iters_done0 > 0) {
+            HIP_TRY(hipMemcpy(req.params.delta_hist, delta_dev, iters_done0 * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        if (req.params.iters_done) *req.params.iters_done = iters_done0;
+        int bad = 0;
+        HIP_TRY(hipMemcpy(&bad, flag, sizeof(int), hipMemcpyDeviceToHost));
+        return bad ? CGDIR_E_NONFINITE : CGDIR_OK;
+    }
+};
+
+// ------------------------------------------------------------------ serving state
+
+struct cgdir_ctx::Request {
+    uint64_t ticket = 0;
+    Job job;
+    int state = CGDIR_QUEUED;
+    int error = CGDIR_OK;
+    int64_t t_submit = 0, t_admit = 0, t_done = 0;
+    int level = 0, iter = 0;   // progress mirrored for cgdir_poll (under ctx->mu)
+    double last_delta = 0.0;
+    hipEvent_t done_ev = nullptr;
+    bool emitted = false;
+};
+
+namespace cgdir {
+namespace {
+
+void finish_request(cgdir_ctx::Request *r, int code)
+{
+    r->job.release();
+    r->error = code;
+    r->state = code == CGDIR_OK ? CGDIR_DONE : (code == CGDIR_E_CANCELLED ? CGDIR_CANCELLED : CGDIR_FAILED);
+    r->t_done = now_ns();
+}
+
+// The serving loop: FIFO admission by pool footprint and free slots, then ticks in which
+// every admitted request advances one iteration; a request that finishes is copied out
+// and its slot and memory are recycled once its completion event has fired.  Events used
+// here belong to this thread alone.
+void scheduler(cgdir_ctx *c)
+{
+    hipSetDevice(c->device);
+    std::vector<hipEvent_t> spare;
+    auto get_ev = [&]() -> hipEvent_t {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return e;
+    };
+    std::vector<cgdir_ctx::Request *> active;
+    std::deque<hipEvent_t> ticks;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(c->mu);
+            // admission, in arrival order
+            while (!c->queue.empty() && (int)active.size() < c->max_slots) {
+                auto it = c->reqs.find(c->queue.front());
+                if (it == c->reqs.end() || it->second->state != CGDIR_QUEUED) {
+                    c->queue.pop_front();
+                    continue;
+                }
+                cgdir_ctx::Request *r = it->second.get();
+                int rc = r->job.allocate();
+                if (rc == CGDIR_E_NOMEM) break;  // the head of the queue waits for memory
+                c->queue.pop_front();
+                if (rc == CGDIR_OK) {
+                    std::lock_guard<std::mutex> lg(c->launch_mu);
+                    rc = r->job.setup();
+                }
+                if (rc != CGDIR_OK) {
+                    finish_request(r, rc);
+                    c->cv.notify_all();
+                    continue;
+                }
+                r->state = CGDIR_RUNNING;
+                r->t_admit = now_ns();
+                active.push_back(r);
+            }
+            if (active.empty()) {
+                if (c->stopping && c->queue.empty()) break;
+                c->cv.wait_for(lk, std::chrono::milliseconds(20));
+                continue;
+            }
+        }
+        // one tick: every admitted request advances one iteration
+        {
+            std::lock_guard<std::mutex> lg(c->launch_mu);
+            for (cgdir_ctx::Request *r : active) {
+                if (r->job.finished) continue;
+                int rc = r->job.advance(1, true);
+                if (rc != CGDIR_OK) {
+                    r->job.finished = true;
+                    r->error = rc;
+                }
+                if (r->job.finished && !r->emitted) {
+                    if (r->error == CGDIR_OK) r->error = r->job.emit();
+                    r->done_ev = get_ev();
+                    if (r->done_ev) hipEventRecord(r->done_ev, c->stream);
+                    r->emitted = true;
+                }
+            }
+            hipEvent_t te = get_ev();
+            if (te) {
+                hipEventRecord(te, c->stream);
+                ticks.push_back(te);
+            }
+        }
+        while (ticks.size() > 2) {  // bounded look-ahead of queued ticks
+            hipEventSynchronize(ticks.front());
+            spare.push_back(ticks.front());
+            ticks.pop_front();
+        }
+        // progress and completions
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (size_t i = 0; i < active.size();) {
+            cgdir_ctx::Request *r = active[i];
+            r->level = r->job.level;
+            r->iter = r->job.iter;
+            if (!r->job.delta_host.empty()) r->last_delta = r->job.delta_host.back();
+            if (r->emitted && (!r->done_ev || hipEventQuery(r->done_ev) == hipSuccess)) {
+                const int rc = r->error != CGDIR_OK ? r->error : r->job.conclude();
+                if (r->done_ev) spare.push_back(r->done_ev);
+                r->done_ev = nullptr;
+                finish_request(r, rc);
+                active.erase(active.begin() + i);
+                c->cv.notify_all();
+            } else {
+                ++i;
+            }
+        }
+    }
+    for (hipEvent_t e : ticks) {
+        hipEventSynchronize(e);
+        spare.push_back(e);
+    }
+    for (hipEvent_t e : spare) hipEventDestroy(e);
+}
+
+}  // namespace
+}  // namespace cgdir
+
+// ====================================================================== C-ABI
+
+extern "C" {
+
+void cgdir_params_default(cgdir_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->levels = 1;
+    for (int l = 0; l < CGDIR_MAX_LEVELS; ++l) p->iters[l] = 100;
+    p->contour_level_mask = 1u;
+    p->sigma_fluid = 1.f;
+    p->sigma_diff = 1.f;
+    p->restrict_sigma = 1.f;
+    for (int i = 0; i < CGDIR_MAX_STRUCTS; ++i) {
+        p->lambda[i] = 1e-3f;
+        p->sign[i] = 1;
+    }
+    p->intensity_offset = 1000.f;
+    p->stop_mode = 0;
+    p->stop_eps = 1e-4f;
+    p->stop_window = 10;
+    p->norm_range = 2500.f;
+    p->uroi_margin[0] = 5;
+    p->uroi_margin[1] = 5;
+    p->uroi_margin[2] = 4;
+    p->initial_dvf = nullptr;
+    p->initial_dvf_where = CGDIR_DEVICE;
+    p->delta_hist = nullptr;
+    p->iters_done = nullptr;
+}
+
+const char *cgdir_strerror(int code)
+{
+    switch (code) {
+    case CGDIR_OK: return "ok";
+    case CGDIR_E_INVAL: return "invalid argument";
+    case CGDIR_E_NOMEM: return "pool cannot hold the request";
+    case CGDIR_E_HIP: return "HIP runtime error";
+    case CGDIR_E_BUSY: return "busy";
+    case CGDIR_E_NOTFOUND: return "unknown ticket";
+    case CGDIR_E_CANCELLED: return "cancelled";
+    case CGDIR_E_NONFINITE: return "non-finite field";
+    case CGDIR_E_UNIMPL: return "not implemented";
+    case CGDIR_E_TIMEOUT: return "timed out";
+    default: return "unknown error";
+    }
+}
+
+size_t cgdir_footprint(int nx, int ny, int nz, int k, const cgdir_params *params)
+{
+    cgdir_params def;
+    if (!params) {
+        cgdir_params_default(&def);
+        params = &def;
+    }
+    if (nx < 1 || ny < 1 || nz < 1 || k < 0 || k > CGDIR_MAX_STRUCTS) return 0;
+    if (params->levels < 1 || params->levels > CGDIR_MAX_LEVELS) return 0;
+    return footprint_bytes(Dims{nx, ny, nz}, k, *params, false, Tuning{});
+}
+
+int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
+{
+    if (!out || !desc || desc->max_slots < 1 || desc->device < 0) return CGDIR_E_INVAL;
+    if (!desc->pool && desc->pool_bytes == 0) return CGDIR_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device >= ndev) return CGDIR_E_HIP;
+    if (hipSetDevice(desc->device) != hipSuccess) return CGDIR_E_HIP;
+    std::unique_ptr<cgdir_ctx> c(new cgdir_ctx());
+    c->device = desc->device;
+    c->max_slots = desc->max_slots;
+    c->profile = (desc->flags & CGDIR_CTX_PROFILE) != 0;
+    if (desc->stream) {
+        c->stream = (hipStream_t)desc->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return CGDIR_E_HIP;
+        c->own_stream = true;
+    }
+    void *pool = desc->pool;
+    if (!pool) {
+        if (hipMalloc(&c->own_pool, desc->pool_bytes) != hipSuccess) {
+            if (c->own_stream) hipStreamDestroy(c->stream);
+            return CGDIR_E_NOMEM;
+        }
+        pool = c->own_pool;
+    }
+    c->pool.init((char *)pool, desc->pool_bytes);
+    *out = c.release();
+    return CGDIR_OK;
+}
+
+int cgdir_destroy(cgdir_ctx *c)
+{
+    if (!c) return CGDIR_E_INVAL;
+    hipSetDevice(c->device);
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (uint64_t t : c->queue) {
+            auto it = c->reqs.find(t);
+            if (it != c->reqs.end() && it->second->state == CGDIR_QUEUED)
+                finish_request(it->second.get(), CGDIR_E_CANCELLED);
+        }
+        c->queue.clear();
+        c->stopping = true;
+    }
+    c->cv.notify_all();
+    if (c->sched_started) c->sched.join();
+    hipStreamSynchronize(c->stream);
+    {
+        std::lock_guard<std::mutex> g(c->prof_mu);
+        drain_profile(c);
+        for (hipEvent_t e : c->spare_events) hipEventDestroy(e);
+        c->spare_events.clear();
+    }
+    if (c->own_pool) hipFree(c->own_pool);
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return CGDIR_OK;
+}
+
+int cgdir_register(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume *moving,
+                   const cgdir_masks *target_masks, const cgdir_masks *moving_masks, const cgdir_params *params,
+                   float *dvf_out, int dvf_where)
+{
+    if (!c || !target || !moving || !params) return CGDIR_E_INVAL;
+    cgdir_request r{};
+    r.target = *target;
+    r.moving = *moving;
+    static const cgdir_masks none = {0, nullptr, CGDIR_DEVICE};
+    r.target_masks = target_masks ? *target_masks : none;
+    r.moving_masks = moving_masks ? *moving_masks : none;
+    r.params = *params;
+    r.dvf_out = dvf_out;
+    r.dvf_where = dvf_where;
+    hipSetDevice(c->device);
+    Job job;
+    CG_TRY(job.init(c, r));
+    CG_TRY(job.allocate());
+    int rc;
+    {
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        rc = job.setup();
+        if (rc == CGDIR_OK) rc = job.advance(1 << 30, true);
+        if (rc == CGDIR_OK) rc = job.emit();
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == CGDIR_OK) rc = CGDIR_E_HIP;
+    if (rc == CGDIR_OK) rc = job.conclude();
+    job.release();
+    return rc;
+}
+
+int cgdir_register_batch(cgdir_ctx *c, int n, const cgdir_request *reqs, int *status)
+{
+    if (!c || n < 0 || (n > 0 && !reqs)) return CGDIR_E_INVAL;
+    hipSetDevice(c->device);
+    std::vector<std::unique_ptr<Job>> jobs;
+    int first = CGDIR_OK;
+    std::vector<int> st(n, CGDIR_OK);
+    for (int i = 0; i < n; ++i) {
+        std::unique_ptr<Job> j(new Job());
+        st[i] = j->init(c, reqs[i]);
+        if (st[i] == CGDIR_OK) st[i] = j->allocate();
+        jobs.push_back(std::move(j));
+    }
+    for (int i = 0; i < n; ++i)
+        if (st[i] == CGDIR_E_NOMEM) {  // all pairs are resident together
+            for (auto &j : jobs) j->release();
+            if (status)
+                for (int q = 0; q < n; ++q) status[q] = st[q] == CGDIR_OK ? CGDIR_E_NOMEM : st[q];
+            return CGDIR_E_NOMEM;
+        }
+    {
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        for (int i = 0; i < n; ++i)
+            if (st[i] == CGDIR_OK) st[i] = jobs[i]->setup();
+        bool more = true;
+        while (more) {  // one iteration of every unfinished pair per round
+            more = false;
+            for (int i = 0; i < n; ++i) {
+                if (st[i] != CGDIR_OK || jobs[i]->finished) continue;
+                st[i] = jobs[i]->advance(1, true);
+                if (st[i] == CGDIR_OK && jobs[i]->finished) st[i] = jobs[i]->emit();
+                more = more || (st[i] == CGDIR_OK && !jobs[i]->finished);
+            }
+        }
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) first = CGDIR_E_HIP;
+    for (int i = 0; i < n; ++i) {
+        if (st[i] == CGDIR_OK) st[i] = jobs[i]->conclude();
+        jobs[i]->release();
+        if (first == CGDIR_OK && st[i] != CGDIR_OK) first = st[i];
+        if (status) status[i] = st[i];
+    }
+    return first;
+}
+
+int cgdir_warp(cgdir_ctx *c, const cgdir_volume *src, const float *dvf, int mode, void *out)
+{
+    if (!c || !src || !src->data || !dvf || !out) return CGDIR_E_INVAL;
+    if (src->nx < 1 || src->ny < 1 || src->nz < 1 || (int64_t)src->nx * src->ny * src->nz > (int64_t(1) << 30))
+        return CGDIR_E_INVAL;
+    if (mode != CGDIR_WARP_LINEAR && mode != CGDIR_WARP_MASK) return CGDIR_E_INVAL;
+    if (src->where != CGDIR_HOST && src->where != CGDIR_DEVICE) return CGDIR_E_INVAL;
+    hipSetDevice(c->device);
+    const Dims d{src->nx, src->ny, src->nz};
+    const int64_t n = d.n();
+    const size_t esz = mode == CGDIR_WARP_LINEAR ? sizeof(float) : 1;
+    const bool host = src->where == CGDIR_HOST;
+    std::vector<void *> tmp;
+    auto take = [&](size_t b) {
+        void *p = c->pool.alloc(b);
+        if (p) tmp.push_back(p);
+        return p;
+    };
+    auto done = [&](int rc) {
+        for (void *p : tmp) c->pool.release(p);
+        return rc;
+    };
+    const void *s_dev = src->data;
+    const float *u_dev = dvf;
+    void *o_dev = out;
+    std::lock_guard<std::mutex> lg(c->launch_mu);
+    if (host) {
+        void *a = take(n * esz), *b = take(3 * n * sizeof(float)), *o = take(n * esz);
+        if (!a || !b || !o) return done(CGDIR_E_NOMEM);
+        if (hipMemcpyAsync(a, src->data, n * esz, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(b, dvf, 3 * n * sizeof(float), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return done(CGDIR_E_HIP);
+        s_dev = a;
+        u_dev = (const float *)b;
+        o_dev = o;
+    }
+    const float *u3[3] = {u_dev, u_dev + n, u_dev + 2 * n};
+    hipError_t e = timed(c, K_WARP, (double)n, [&] {
+        return mode == CGDIR_WARP_LINEAR ? launch_warp_linear((const float *)s_dev, d, u3, (float *)o_dev, c->stream)
+                                         : launch_warp_mask((const uint8_t *)s_dev, d, u3, (uint8_t *)o_dev, c->stream);
+    });
+    if (e != hipSuccess) return done(CGDIR_E_HIP);
+    if (host && hipMemcpyAsync(out, o_dev, n * esz, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return done(CGDIR_E_HIP);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return done(CGDIR_E_HIP);
+    return done(CGDIR_OK);
+}
+
+int cgdir_submit(cgdir_ctx *c, const cgdir_request *req, uint64_t *ticket)
+{
+    if (!c || !req || !ticket) return CGDIR_E_INVAL;
+    std::unique_ptr<cgdir_ctx::Request> r(new cgdir_ctx::Request());
+    CG_TRY(r->job.init(c, *req));
+    if (r->job.need() > c->pool.size()) return CGDIR_E_NOMEM;
+    r->t_submit = now_ns();
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->stopping) return CGDIR_E_INVAL;
+    const uint64_t t = c->next_ticket++;
+    r->ticket = t;
+    c->reqs[t] = std::move(r);
+    c->queue.push_back(t);
+    *ticket = t;
+    if (!c->sched_started) {
+        c->sched = std::thread(scheduler, c);
+        c->sched_started = true;
+    }
+    c->cv.notify_all();
+    return CGDIR_OK;
+}
+
+int cgdir_poll(cgdir_ctx *c, uint64_t ticket, cgdir_status *st)
+{
+    if (!c || !st) return CGDIR_E_INVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->reqs.find(ticket);
+    if (it == c->reqs.end()) return CGDIR_E_NOTFOUND;
+    const cgdir_ctx::Request &r = *it->second;
+    st->state = r.state;
+    st->error = r.error;
+    st->level = r.level;
+    st->iter = r.iter;
+    st->last_delta = r.last_delta;
+    st->t_submit_ns = r.t_submit;
+    st->t_admit_ns = r.t_admit;
+    st->t_done_ns = r.t_done;
+    return CGDIR_OK;
+}
+
+int cgdir_cancel(cgdir_ctx *c, uint64_t ticket)
+{
+    if (!c) return CGDIR_E_INVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->reqs.find(ticket);
+    if (it == c->reqs.end()) return CGDIR_E_NOTFOUND;
+    if (it->second->state != CGDIR_QUEUED) return CGDIR_E_BUSY;
+    finish_request(it->second.get(), CGDIR_E_CANCELLED);
+    c->cv.notify_all();
+    return CGDIR_OK;
+}
+
+int cgdir_wait(cgdir_ctx *c, uint64_t ticket, int64_t timeout_ns)
+{
+    if (!c) return CGDIR_E_INVAL;
+    std::unique_lock<std::mutex> lk(c->mu);
+    auto final_state = [&](int s) { return s == CGDIR_DONE || s == CGDIR_FAILED || s == CGDIR_CANCELLED; };
+    auto it = c->reqs.find(ticket);
+    if (it == c->reqs.end()) return CGDIR_E_NOTFOUND;
+    cgdir_ctx::Request *r = it->second.get();
+    auto pred = [&] { return final_state(r->state); };
+    if (timeout_ns < 0) {
+        c->cv.wait(lk, pred);
+    } else if (!c->cv.wait_for(lk, std::chrono::nanoseconds(timeout_ns), pred)) {
+        return CGDIR_E_TIMEOUT;
+    }
+    return r->error;
+}
+
+int cgdir_kernel_stats(cgdir_ctx *c, cgdir_kernel_stat *out, int cap, int reset)
+{
+    if (!c || (cap > 0 && !out)) return CGDIR_E_INVAL;
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    drain_profile(c);
+    int n = 0;
+    for (int i = 0; i < K_COUNT && n < cap; ++i) {
+        if (c->launches[i] == 0) continue;
+        std::memset(out[n].name, 0, sizeof(out[n].name));
+        std::strncpy(out[n].name, kKernelNames[i], sizeof(out[n].name) - 1);
+        out[n].launches = c->launches[i];
+        out[n].total_ms = c->total_ms[i];
+        out[n].voxels = c->voxels[i];
+        ++n;
+    }
+    if (reset)
+        for (int i = 0; i < K_COUNT; ++i) {
+            c->launches[i] = 0;
+            c->total_ms[i] = 0.0;
+            c->voxels[i] = 0.0;
+        }
+    return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every entry point include/cgdir.h declares; host-only
+calls (defaults, footprint, error strings, argument rejection) work without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cgdir.h")).read()
+    return sorted(set(re.findall(r"\b(cgdir_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    from paper_1301_0970_amd import cgdir
+    names = _declared()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(cgdir.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(cgdir.SYMBOLS)
+
+
+def test_defaults_follow_the_paper():
+    from paper_1301_0970_amd import cgdir
+    p = cgdir.params_default()
+    assert p.levels == 1 and p.iters[0] == 100
+    assert p.sigma_fluid == 1.0 and p.sigma_diff == 1.0          # unit sigma (section 2.2)
+    assert p.lambda_[0] == pytest.approx(1e-3)                   # lambda ~ 1e-3 (section 2.2)
+    assert p.stop_eps == pytest.approx(1e-4) and p.stop_window == 10
+    assert list(p.uroi_margin) == [5, 5, 4]                      # 1 cm at 1.97x1.97x2.5 mm
+    assert p.contour_level_mask == 1 and p.intensity_offset == 1000.0
+
+
+def test_footprint():
+    from paper_1301_0970_amd import cgdir
+    p = cgdir.make_params(levels=3, iters=(150, 150, 150))
+    n = 512 * 512 * 128
+    fp = cgdir.footprint(512, 512, 128, 8, p)
+    # u, du, u_c (36 B/voxel) + bit-planes (2 B) + coarse images (8 B x (1/8 + 1/64))
+    assert 38 * n <= fp <= 40 * n
+    assert cgdir.footprint(512, 512, 128, 0, p) < fp
+    assert cgdir.footprint(0, 5, 5, 1, p) == 0
+    assert cgdir.footprint(5, 5, 5, 9, p) == 0
+
+
+def test_strerror_and_codes():
+    from paper_1301_0970_amd import cgdir
+    assert cgdir.strerror(0) == "ok"
+    assert "pool" in cgdir.strerror(cgdir.E_NOMEM)
+    assert cgdir.strerror(12345) == "unknown error"
+
+
+def test_create_rejects_bad_descriptions():
+    from paper_1301_0970_amd import cgdir
+    lib = cgdir.LIB
+    h = ctypes.c_void_p()
+    d = cgdir.ctx_desc(0, None, None, 0, 1, 0)       # no pool and no size
+    assert lib.cgdir_create(ctypes.byref(h), ctypes.byref(d)) == cgdir.E_INVAL
+    d = cgdir.ctx_desc(0, None, None, 1 << 20, 0, 0)  # no slots
+    assert lib.cgdir_create(ctypes.byref(h), ctypes.byref(d)) == cgdir.E_INVAL
+    assert lib.cgdir_destroy(None) == cgdir.E_INVAL
+    assert lib.cgdir_register(None, None, None, None, None, None, None, 0) == cgdir.E_INVAL

@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances are those of the method's acceptance bar: one teacher-forced iteration
+agrees to 1e-4 voxel (max-abs over the field); a full registration to 1e-2 voxel, with
+the warped moving images within 1e-3 of the 2500 HU intensity range (2.5 HU RMS).
+"""
+import numpy as np
+import pytest
+
+from paper_1301_0970_amd import phantom as P
+
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-4
+FINAL_TOL = 1e-2
+WARP_RMS_TOL = 2.5
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1301_0970_amd import cgdir
+    assert torch.cuda.is_available()
+    c = cgdir.Context(6 << 30, max_slots=4)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def gpu_register(ctx, pair, prm, initial=None, delta=False, masks=True):
+    from paper_1301_0970_amd import cgdir  # noqa: F401
+    tm = dev(pair.target_masks) if masks and pair.k else None
+    mm = dev(pair.moving_masks) if masks and pair.k else None
+    res = ctx.register(dev(pair.target), dev(pair.moving), tm, mm, prm,
+                       initial=dev(initial) if initial is not None else None, delta=delta)
+    if delta:
+        u, h, n = res
+        return u.cpu().numpy(), np.array(h), n
+    return res.cpu().numpy()
+
+
+def oracle_step(orc, pair, u0, sigma_f, sigma_d, lambdas, signs, c0=1000.0):
+    Ip = [orc.modified_image(pair.moving, pair.moving_masks[i], signs[i], c0) for i in range(len(lambdas))]
+    Tp = [orc.modified_image(pair.target, pair.target_masks[i], signs[i], c0) for i in range(len(lambdas))]
+    u, _ = orc.step(pair.moving, pair.target, Ip, Tp, lambdas, sigma_f, sigma_d, u0.astype(np.float64))
+    return u
+
+
+STEP_CASES = [
+    # name, generator kwargs, k, sigma, field amplitude
+    ("plain k1 ragged", dict(kind="plain", dims=(97, 45, 23), amp=3.0), 1, 1.0, 2.5),
+    ("demons k0", dict(kind="plain", dims=(80, 72, 33), amp=3.0), 0, 1.0, 2.0),
+    ("head_neck k3 sigma1.5", dict(kind="head_neck", dims=(130, 70, 40), amp=4.0, k=3), 3, 1.5, 3.0),
+    ("head_neck k5 sigma1.5", dict(kind="head_neck", dims=(128, 96, 48), amp=5.0, k=5), 5, 1.5, 4.0),
+    ("pelvis k8", dict(kind="pelvis", dims=(160, 136, 48), amp=6.0, k=8, bulge=3.0), 8, 1.0, 6.0),
+    ("pelvis k2 thin", dict(kind="pelvis", dims=(200, 66, 9), amp=2.0, k=2, bulge=0.0), 2, 1.0, 1.5),
+]
+
+
+def _make(kind, **kw):
+    if kind == "plain":
+        return P.plain_pair(**kw)
+    if kind == "head_neck":
+        return P.head_neck_pair(**kw)
+    return P.pelvis_pair(**kw)
+
+
+@pytest.mark.parametrize("name,kw,k,sigma,famp", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_teacher_forced_step(ctx, orc, name, kw, k, sigma, famp):
+    """One iteration from the same fp32 field u^n: GPU vs FP64 oracle, <= 1e-4 voxel."""
+    from paper_1301_0970_amd import cgdir
+    pair = _make(**kw)
+    if k == 0:
+        pair.target_masks = pair.target_masks[:0]
+        pair.moving_masks = pair.moving_masks[:0]
+        pair.signs = ()
+    u0 = P.random_smooth_field(pair.dims, famp, 101)
+    lam = [1e-3 * (1 + i) for i in range(pair.k)]
+    sg = [1 if i % 3 else -1 for i in range(pair.k)]
+    prm = cgdir.make_params(levels=1, iters=(1,), sigma_fluid=sigma, sigma_diff=sigma, lambdas=lam, signs=sg)
+    say("step case %s dims %s k %d" % (name, pair.dims, pair.k))
+    ug = gpu_register(ctx, pair, prm, initial=u0)
+    uo = oracle_step(orc, pair, u0, sigma, sigma, lam, sg)
+    err = np.abs(ug - uo).max()
+    say("  max |du| %.3g  max err %.3g" % (np.abs(uo - u0).max(), err))
+    assert err <= STEP_TOL
+
+
+def test_step_with_different_sigmas(ctx, orc):
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(100, 90, 30), amp=4.0, k=2)
+    u0 = P.random_smooth_field(pair.dims, 3.0, 7)
+    prm = cgdir.make_params(levels=1, iters=(1,), sigma_fluid=2.0, sigma_diff=0.6, lambdas=[2e-3, 1e-3])
+    say("step sigma_f 2.0 sigma_d 0.6")
+    ug = gpu_register(ctx, pair, prm, initial=u0)
+    uo = oracle_step(orc, pair, u0, 2.0, 0.6, [2e-3, 1e-3], [1, 1])
+    assert np.abs(ug - uo).max() <= STEP_TOL
+
+
+def test_full_run_plain(ctx, orc):
+    """Config 1 in full: 64x64x32, 1 level x 100 iterations, k = 1."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair()
+    say("full run plain 64x64x32 x100")
+    ug = gpu_register(ctx, pair, cgdir.params_for_pair(pair))
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks, orc.params_for(pair))
+    err = np.abs(ug - uo).max()
+    wg = orc.warp(pair.moving, ug)
+    wo = orc.warp(pair.moving, uo)
+    rms = np.sqrt(((wg - wo) ** 2).mean())
+    say("  final max err %.3g voxel, warped rms %.3g HU" % (err, rms))
+    assert err <= FINAL_TOL and rms <= WARP_RMS_TOL
+
+
+def test_full_run_pyramid(ctx, orc):
+    """Three levels (demons on the coarse two, CG-DIR at the finest) on a ragged
+    head-and-neck-like pair."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(99, 83, 45), amp=5.0, k=4, levels=3, iters=30)
+    say("full run pyramid 99x83x45 3x30")
+    ug = gpu_register(ctx, pair, cgdir.params_for_pair(pair))
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks, orc.params_for(pair))
+    err = np.abs(ug - uo).max()
+    rms = np.sqrt(((orc.warp(pair.moving, ug) - orc.warp(pair.moving, uo)) ** 2).mean())
+    say("  final max err %.3g voxel, warped rms %.3g HU" % (err, rms))
+    assert err <= FINAL_TOL and rms <= WARP_RMS_TOL
+
+
+def test_restrict_and_prolong_through_schedule(ctx, orc):
+    """levels=2 with iterations (0 finest, 1 coarse): the output is the prolonged first
+    coarse step on the restricted images -- checks restriction, the coarse demons step
+    and prolongation at 1e-4."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.pelvis_pair(dims=(77, 64, 31), amp=3.0, k=3, levels=2, iters=1, bulge=0.0)
+    prm = cgdir.params_for_pair(pair, iters=(0, 1))
+    say("pyramid schedule (0, 1)")
+    ug = gpu_register(ctx, pair, prm)
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, iters=(0, 1)))
+    assert np.abs(uo).max() > 0.05
+    assert np.abs(ug - uo).max() <= STEP_TOL * 2  # prolongation doubles the coarse field
+
+
+def test_identity_stays_zero(ctx):
+    """P4 on the GPU: identical images and masks give exactly u = 0."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair(dims=(70, 50, 20), amp=2.0)
+    pair.moving = pair.target.copy()
+    pair.moving_masks = pair.target_masks.copy()
+    say("identity")
+    ug = gpu_register(ctx, pair, cgdir.params_for_pair(pair, levels=2, iters=(5, 5)))
+    assert np.all(ug == 0.0)
+
+
+def test_delta_history_and_stop_rule(ctx, orc):
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair(dims=(64, 48, 24), amp=2.0, iters=40)
+    prm = cgdir.params_for_pair(pair)
+    say("delta history")
+    ug, hg, n = gpu_register(ctx, pair, prm, delta=True)
+    uo, ho, no = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                              orc.params_for(pair), want_delta=True)
+    assert n == no == 40
+    np.testing.assert_allclose(hg, ho, rtol=1e-4)
+    # stopping: pick eps between the two largest progress values at the check points so
+    # that no check sits near a tie; the GPU decision must be valid on its own history
+    # and equal the oracle's
+    d = sorted(ho[m - 10] - ho[m] for m in (19, 29, 39))
+    eps = 0.5 * (d[1] + d[2])
+    say("stop rule eps %.3g" % eps)
+    prm = cgdir.params_for_pair(pair, stop_mode=1, stop_eps=eps)
+    _, hs, ns = gpu_register(ctx, pair, prm, delta=True)
+    first = next((m for m in range(19, 40, 10) if hs[m - 10] - hs[m] <= float(np.float32(eps))), 39)
+    assert ns == first + 1 and ns < 40
+    _, _, no2 = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                             orc.params_for(pair, stop_mode=1, stop_eps=eps), want_delta=True)
+    assert ns == no2
+
+
+def test_auto_sign(ctx, orc):
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(96, 80, 32), amp=3.0, k=3)
+    # make structure 1 darker than its surroundings in the target
+    t = pair.target.copy()
+    t[pair.target_masks[1] == 1] -= 60.0
+    pair.target = t
+    u0 = P.random_smooth_field(pair.dims, 2.0, 3)
+    prm = cgdir.make_params(levels=1, iters=(1,), sigma_fluid=1.5, sigma_diff=1.5, lambdas=[5e-3] * 3,
+                            signs=[0, 0, 0])
+    say("auto sign")
+    ug = gpu_register(ctx, pair, prm, initial=u0)
+    signs = [orc.auto_sign(pair.target, pair.target_masks[i]) for i in range(3)]
+    assert signs[1] == -1
+    uo = oracle_step(orc, pair, u0, 1.5, 1.5, [5e-3] * 3, signs)
+    assert np.abs(ug - uo).max() <= STEP_TOL
+
+
+def test_warp_linear_and_mask(ctx, orc):
+    import torch
+    from paper_1301_0970_amd import cgdir
+    rng = np.random.default_rng(5)
+    dims = (67, 41, 19)
+    src = rng.normal(0, 300, dims[::-1]).astype(np.float32)
+    u = P.random_smooth_field(dims, 4.0, 11)
+    say("warp linear")
+    out = ctx.warp(dev(src), dev(u)).cpu().numpy()
+    ref = orc.warp(src, u)
+    assert np.abs(out - ref).max() <= 1e-3
+    # host buffers take the same path through a device copy
+    out_h = ctx.warp(torch.from_numpy(src), torch.from_numpy(u)).numpy()
+    np.testing.assert_array_equal(out_h, out)
+    m = (rng.uniform(size=dims[::-1]) > 0.7).astype(np.uint8)
+    say("warp mask")
+    mo = ctx.warp(dev(m), dev(u), mode=cgdir.WARP_MASK).cpu().numpy()
+    ref_val = orc.warp(m.astype(np.float64), u)
+    decided = np.abs(ref_val - 0.5) > 1e-5
+    np.testing.assert_array_equal(mo[decided], (ref_val >= 0.5)[decided].astype(np.uint8))
+
+
+def test_host_inputs_match_device_inputs(ctx):
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(64, 64, 24), amp=3.0, k=2, levels=2, iters=5)
+    prm = cgdir.params_for_pair(pair)
+    say("host inputs")
+    ud = gpu_register(ctx, pair, prm)
+    uh = ctx.register(torch.from_numpy(pair.target), torch.from_numpy(pair.moving),
+                      torch.from_numpy(pair.target_masks), torch.from_numpy(pair.moving_masks), prm).numpy()
+    np.testing.assert_array_equal(ud, uh)
+
+
+def test_invalid_arguments(ctx):
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair(dims=(32, 32, 16), amp=1.0, iters=2)
+    t, m = dev(pair.target), dev(pair.moving)
+    tm, mm = dev(pair.target_masks), dev(pair.moving_masks)
+    say("invalid arguments")
+    with pytest.raises(cgdir.CgdirError) as e:
+        ctx.register(t, m[:8], tm, mm, cgdir.params_for_pair(pair))
+    assert e.value.code == cgdir.E_INVAL
+    with pytest.raises(cgdir.CgdirError) as e:
+        ctx.register(t, m, tm, mm[:0], cgdir.params_for_pair(pair))
+    assert e.value.code == cgdir.E_INVAL
+    for bad in (dict(levels=0), dict(sigma_fluid=5.0), dict(norm_range=0.0), dict(uroi_margin=(9, 1, 1))):
+        with pytest.raises(cgdir.CgdirError) as e:
+            ctx.register(t, m, tm, mm, cgdir.params_for_pair(pair, **bad))
+        assert e.value.code == cgdir.E_INVAL, bad
+    with pytest.raises(cgdir.CgdirError) as e:
+        ctx.register(t, m, tm, mm, cgdir.params_for_pair(pair, contour_level_mask=2))
+    assert e.value.code == cgdir.E_UNIMPL
+    big = torch.zeros((200, 1024, 1024), dtype=torch.float32, device="cuda")
+    with pytest.raises(cgdir.CgdirError) as e:
+        ctx.register(big, big, None, None, cgdir.make_params(levels=1, iters=(1,)))
+    assert e.value.code == cgdir.E_NOMEM
+
+
+def test_nonfinite_input_reported(ctx):
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair(dims=(40, 36, 20), amp=1.0, iters=3)
+    pair.moving = pair.moving.copy()
+    pair.moving[10, 18, 20] = np.nan
+    say("nonfinite")
+    with pytest.raises(cgdir.CgdirError) as e:
+        gpu_register(ctx, pair, cgdir.params_for_pair(pair))
+    assert e.value.code == cgdir.E_NONFINITE

@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of contour-guided demons registration on one MI355X.
+
+One step = one full registration (Algorithm A: pyramid set-up, coarse demons levels,
+finest-level CG-DIR loop) of the synthetic workload, through the C-ABI, with the inputs
+already resident in HBM.  value = voxel-iterations per second, sum over levels of
+(voxels x iterations) / wall time per step.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel (finest-level force) -- algorithmic bytes per launch
+                (bytes per voxel x voxels) over its average launch duration, from HIP
+                events on the library's stream during a profiled pass of the same steps;
+                traffic = HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+                summary in profiles/, when it was taken on the current kernel source.
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload (rank 0 only).
+  served        with --serve: open-loop Poisson arrivals, p50/p99 latency.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per voxel of each finest-level kernel (fields FP32 SoA, mask bit-planes
+# one byte per voxel per side): force reads u (12), I0 (4, gathered about once), T0 (4), the
+# two bit-planes (2) and writes du (12); smooth_compose reads du (12), u (12, gathered near
+# x) and writes u_c (12); smooth reads u_c (12) and writes u (12).
+BYTES_PER_VOXEL = {"force": 34, "smooth_compose": 36, "smooth": 24}
+KERNEL_SYMBOL = {"force": "k_force", "smooth_compose": "k_smooth", "smooth": "k_smooth"}
+
+WORKLOADS = {
+    "pelvis": ("pelvis-like CT 512x512x128, 8 structures (+15 HU), 3 levels x 150 iterations, "
+               "DVF sigma 1", lambda P: P.pelvis_pair()),
+    "head_neck": ("head-and-neck-like CT 256x256x128, 5 structures (+10..30 HU), 3 levels x 100 "
+                  "iterations, DVF sigma 1.5", lambda P: P.head_neck_pair()),
+    "plain": ("nested-ellipsoid phantom 64x64x32, 1 structure, 1 level x 100 iterations",
+              lambda P: P.plain_pair()),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_1301_0970_amd", "csrc", "cgdir_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(workload, kernel):
+    """HBM bytes per launch from profiles/<kernel>_<workload>_pmc.md, if it was measured on
+    the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(pair, seconds_hint=20.0):
+    """The oracle's Algorithm A on the full-size inputs of the workload, with 3 iterations
+    per level instead of the workload's counts."""
+    import oracle
+    it = 3
+    prm = oracle.params_for(pair, iters=(it,) * pair.levels)
+    t0 = time.time()
+    oracle.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks, prm)
+    dt = time.time() - t0
+    vi = 0
+    dims = pair.dims
+    for _ in range(pair.levels):
+        vi += dims[0] * dims[1] * dims[2] * it
+        dims = tuple((n + 1) // 2 for n in dims)
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    return {"value": vi / dt, "unit": "voxel-iter/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 oracle, Algorithm A on the full %dx%dx%d inputs with %d iterations per "
+                      "level (%d levels, %.0f M voxel-iterations, %.1f s)"
+                      % (pair.dims + (it, pair.levels, vi / 1e6, dt))}
+
+
+def served(ctx_cls, cgdir, P, torch, duration, rate, pool_bytes, distinct):
+    """Open-loop Poisson arrivals; each request registers a pair drawn like the batched
+    workload (a pool of `distinct` pre-generated pairs is cycled)."""
+    times, specs = P.serve_schedule(rate=rate, duration=duration)
+    pool_specs = specs[:distinct]
+    pairs = [P.from_spec(s) for s in pool_specs]
+    dev = torch.device("cuda")
+    items = [(torch.from_numpy(p.target).to(dev), torch.from_numpy(p.moving).to(dev),
+              torch.from_numpy(p.target_masks).to(dev), torch.from_numpy(p.moving_masks).to(dev))
+             for p in pairs]
+    outs = [torch.empty((3,) + p.target.shape, device=dev) for p in pairs]
+    prms = [cgdir.params_for_pair(p) for p in pairs]
+    lat = []
+    with ctx_cls(pool_bytes, max_slots=8) as ctx:
+        # one-at-a-time reference on the same GPU
+        t0 = time.time()
+        for it, pr, o in zip(items, prms, outs):
+            ctx.register(*it, pr, o)
+        serial_s = (time.time() - t0) / len(items)
+        start = time.time()
+        tickets = []
+        for i, t in enumerate(times):
+            now = time.time() - start
+            if t > now:
+                time.sleep(t - now)
+            j = i % len(items)
+            tickets.append(ctx.submit(*items[j], prms[j], torch.empty_like(outs[j])))
+        for t in tickets:
+            rc = ctx.wait(t)
+            if rc != cgdir.OK:
+                raise RuntimeError("served request failed: %s" % cgdir.strerror(rc))
+        end = time.time()
+        for t in tickets:
+            st = ctx.poll(t)
+            lat.append((st.t_done_ns - st.t_submit_ns) / 1e6)
+    import numpy as np
+    lat = np.array(lat)
+    return {"requests": len(lat), "rate_per_s": rate, "duration_s": duration,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "registrations_per_s": len(lat) / (end - start),
+            "serial_ms_per_registration": serial_s * 1e3, "distinct_pairs": len(items)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="pelvis", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="also run the served workload")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (calibrates HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: registration pairs shard across GPUs with no "
+              "exchange, so there is no multi-GPU path to time (asked for --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1301_0970_amd import cgdir, phantom as P
+
+    if args.copy_probe:
+        n = args.copy_probe << 18   # float32 elements
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}))
+        return
+
+    desc, make = WORKLOADS[args.workload]
+    log("generating %s" % args.workload)
+    pair = make(P)
+    dev = torch.device("cuda", 0)
+    t = torch.from_numpy(pair.target).to(dev)
+    m = torch.from_numpy(pair.moving).to(dev)
+    tm = torch.from_numpy(pair.target_masks).to(dev)
+    mm = torch.from_numpy(pair.moving_masks).to(dev)
+    prm = cgdir.params_for_pair(pair)
+    out = torch.empty((3,) + pair.target.shape, device=dev)
+    pool = cgdir.footprint(*pair.dims, pair.k, prm) + (64 << 20)
+    vi = pair.voxel_iterations()
+
+    with cgdir.Context(pool) as ctx:
+        for i in range(args.warmup):
+            log("warmup %d" % i)
+            ctx.register(t, m, tm, mm, prm, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ctx.register(t, m, tm, mm, prm, out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        log("timed %d steps: %.2f ms/step" % (args.steps, dt * 1e3))
+
+    # profiled pass of the same steps: per-kernel HIP events on the library's stream
+    with cgdir.Context(pool, profile=True) as ctx:
+        ctx.register(t, m, tm, mm, prm, out)
+        ctx.kernel_stats(reset=True)
+        for i in range(args.steps):
+            ctx.register(t, m, tm, mm, prm, out)
+        torch.cuda.synchronize()
+        stats = ctx.kernel_stats()
+    finest = {s["name"].split("@")[0]: s for s in stats if s["name"].endswith("@L0")}
+    dom = max((n for n in finest if n in BYTES_PER_VOXEL), key=lambda n: finest[n]["total_ms"])
+    s = finest[dom]
+    bpv = BYTES_PER_VOXEL[dom] - (2 if dom == "force" and pair.k == 0 else 0)
+    per_launch_bytes = bpv * s["voxels"] / s["launches"]
+    avg_ms = s["total_ms"] / s["launches"]
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = read_traffic(args.workload, dom)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "%s (%s), finest level" % (dom, KERNEL_SYMBOL[dom]),
+                "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": per_launch_bytes,
+                "bytes_per_voxel": bpv}
+    per_kernel = {x["name"]: {"launches": x["launches"], "avg_ms": round(x["total_ms"] / x["launches"], 5)}
+                  for x in stats}
+
+    result = {
+        "metric": "voxel-iterations/s + HBM GB/s vs roofline; served p50/p99 latency per registration",
+        "value": vi / dt,
+        "unit": "voxel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded phantom standing in for clinical CT)",
+        "config": {"workload": desc, "dims": list(pair.dims), "structures": pair.k,
+                   "levels": pair.levels, "iters": list(pair.iters), "voxel_iterations": vi},
+        "roofline": roofline,
+        "kernels": per_kernel,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(pair)
+    if args.serve:
+        log("served workload")
+        result["served"] = served(cgdir.Context, cgdir, P, torch, args.serve_seconds, 4.0,
+                                  32 << 30, 16)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -208,8 +208,10 @@ size_t cgdir_footprint(int nx, int ny, int nz, int k, const cgdir_params *params
 const char *cgdir_strerror(int code);
 
 /* Per-kernel timing, filled when the context was created with CGDIR_CTX_PROFILE:
- * launches and summed duration (HIP events on the context stream) of each kernel since
- * the last reset.  Returns the number of entries written (<= cap). */
+ * launches, summed duration (HIP events on the context stream) and voxels processed of
+ * each kernel since the last reset.  Kernels of the iteration are reported per pyramid
+ * level as "<kernel>@L<level>" (L0 = finest); set-up kernels by name alone.
+ * Returns the number of entries written (<= cap). */
 typedef struct cgdir_kernel_stat {
     char name[48];
     int64_t launches;

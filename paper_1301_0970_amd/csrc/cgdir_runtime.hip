@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -194,9 +195,10 @@ struct cgdir_ctx {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> spare_events;
-    int64_t launches[K_COUNT] = {};
-    double total_ms[K_COUNT] = {};
-    double voxels[K_COUNT] = {};
+    // statistics per (kernel, pyramid level); level slot 7 = set-up work
+    int64_t launches[K_COUNT * 8] = {};
+    double total_ms[K_COUNT * 8] = {};
+    double voxels[K_COUNT * 8] = {};
 
     // serving
     std::mutex mu;
@@ -241,9 +243,10 @@ void drain_profile(cgdir_ctx *c)  // caller holds prof_mu
     c->pending.clear();
 }
 
-// Runs `fn` (one kernel launch) on the context stream, bracketed by events when profiling.
+// Runs `fn` (one kernel launch) on the context stream, bracketed by events when profiling;
+// `slot` = kernel id * 8 + pyramid level (7 for set-up work).
 template <typename F>
-hipError_t timed(cgdir_ctx *c, int id, double vox, F &&fn)
+hipError_t timed(cgdir_ctx *c, int slot, double vox, F &&fn)
 {
     if (!c->profile) return fn();
     std::lock_guard<std::mutex> g(c->prof_mu);
@@ -253,7 +256,7 @@ hipError_t timed(cgdir_ctx *c, int id, double vox, F &&fn)
     hipEventRecord(a, c->stream);
     hipError_t e = fn();
     hipEventRecord(b, c->stream);
-    c->pending.push_back({id, a, b, vox});
+    c->pending.push_back({slot, a, b, vox});
     return e;
 }
 
@@ -500,14 +503,14 @@ struct Job {
                 } else {
                     for (int i = 0; i < k; ++i) planes[i] = m.planes[i];
                 }
-                HIP_TRY(timed(ctx, K_PACK, (double)n0, [&] { return launch_pack_masks(planes, k, n0, bits, s); }));
+                HIP_TRY(timed(ctx, K_PACK * 8 + 7, (double)n0, [&] { return launch_pack_masks(planes, k, n0, bits, s); }));
                 if (m.where == CGDIR_HOST) HIP_TRY(hipStreamSynchronize(s));  // staging reused next side
             }
         }
         uint8_t *rowdist = (uint8_t *)dubuf;  // scratch during setup
         if (delta_on) {
             if (k > 0) {
-                HIP_TRY(timed(ctx, K_UROI, (double)n0,
+                HIP_TRY(timed(ctx, K_UROI * 8 + 7, (double)n0,
                               [&] { return launch_uroi(tbits, d0, req.params.uroi_margin, rowdist, uroi, s); }));
             } else {
                 HIP_TRY(hipMemsetAsync(uroi, 1, n0, s));
@@ -544,7 +547,7 @@ struct Job {
             for (int img = 0; img < 2; ++img) {
                 const float *src = img == 0 ? I0[l - 1] : T0[l - 1];
                 float *dst = (float *)(img == 0 ? I0[l] : T0[l]);
-                HIP_TRY(timed(ctx, K_RESTRICT, (double)din.n(), [&] {
+                HIP_TRY(timed(ctx, K_RESTRICT * 8 + l, (double)din.n(), [&] {
                     hipError_t e = launch_restrict_pass(src, t1, din, 0, wr, Rr, s);
                     if (e == hipSuccess) e = launch_restrict_pass(t1, t2, dx, 1, wr, Rr, s);
                     if (e == hipSuccess) e = launch_restrict_pass(t2, dst, dy, 2, wr, Rr, s);
@@ -574,7 +577,7 @@ struct Job {
         const Dims dc = level_dims(d0, level + 1), df = level_dims(d0, level);
         const float *uc[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
         float *uf[3] = {comp(dubuf, 0), comp(dubuf, 1), comp(dubuf, 2)};
-        HIP_TRY(timed(ctx, K_PROLONG, (double)df.n(), [&] { return launch_prolong(uc, dc, uf, df, ctx->stream); }));
+        HIP_TRY(timed(ctx, K_PROLONG * 8 + level, (double)df.n(), [&] { return launch_prolong(uc, dc, uf, df, ctx->stream); }));
         std::swap(ubuf, dubuf);
         return CGDIR_OK;
     }
@@ -608,9 +611,9 @@ struct Job {
         fa.tz = ctx->tune.force_tz;
         int nblocks = 0;
         const int kp = kp_for(fa.k);
-        HIP_TRY(timed(ctx, K_FORCE, (double)d.n(), [&] { return launch_force(fa, kp, ctx->tune.force_ty, s, &nblocks); }));
+        HIP_TRY(timed(ctx, K_FORCE * 8 + level, (double)d.n(), [&] { return launch_force(fa, kp, ctx->tune.force_ty, s, &nblocks); }));
         if (metric)
-            HIP_TRY(timed(ctx, K_DELTA, 0.0, [&] {
+            HIP_TRY(timed(ctx, K_DELTA * 8 + level, 0.0, [&] {
                 return launch_delta_finalize(partials, nblocks, misc_i64, delta_dev + iter, 0.f, s);
             }));
         SmoothArgs sa{};
@@ -622,7 +625,7 @@ struct Job {
         sa.d = d;
         sa.tz = ctx->tune.smooth_tz;
         for (int m = 0; m <= kMaxRadius; ++m) sa.w[m] = wf[m];
-        HIP_TRY(timed(ctx, K_SMOOTH_COMPOSE, (double)d.n(),
+        HIP_TRY(timed(ctx, K_SMOOTH_COMPOSE * 8 + level, (double)d.n(),
                       [&] { return launch_smooth(sa, Rf, true, ctx->tune.smooth_ty, s); }));
         SmoothArgs sb{};
         for (int c = 0; c < 3; ++c) {
@@ -633,7 +636,7 @@ struct Job {
         sb.d = d;
         sb.tz = ctx->tune.smooth_tz;
         for (int m = 0; m <= kMaxRadius; ++m) sb.w[m] = wd[m];
-        HIP_TRY(timed(ctx, K_SMOOTH, (double)d.n(), [&] { return launch_smooth(sb, Rd, false, ctx->tune.smooth_ty, s); }));
+        HIP_TRY(timed(ctx, K_SMOOTH * 8 + level, (double)d.n(), [&] { return launch_smooth(sb, Rd, false, ctx->tune.smooth_ty, s); }));
         ++iter;
         return CGDIR_OK;
     }
@@ -1078,7 +1081,7 @@ int cgdir_warp(cgdir_ctx *c, const cgdir_volume *src, const float *dvf, int mode
         o_dev = o;
     }
     const float *u3[3] = {u_dev, u_dev + n, u_dev + 2 * n};
-    hipError_t e = timed(c, K_WARP, (double)n, [&] {
+    hipError_t e = timed(c, K_WARP * 8 + 7, (double)n, [&] {
         return mode == CGDIR_WARP_LINEAR ? launch_warp_linear((const float *)s_dev, d, u3, (float *)o_dev, c->stream)
                                          : launch_warp_mask((const uint8_t *)s_dev, d, u3, (uint8_t *)o_dev, c->stream);
     });
@@ -1164,17 +1167,20 @@ int cgdir_kernel_stats(cgdir_ctx *c, cgdir_kernel_stat *out, int cap, int reset)
     std::lock_guard<std::mutex> g(c->prof_mu);
     drain_profile(c);
     int n = 0;
-    for (int i = 0; i < K_COUNT && n < cap; ++i) {
+    for (int i = 0; i < K_COUNT * 8 && n < cap; ++i) {
         if (c->launches[i] == 0) continue;
         std::memset(out[n].name, 0, sizeof(out[n].name));
-        std::strncpy(out[n].name, kKernelNames[i], sizeof(out[n].name) - 1);
+        if (i % 8 == 7)
+            std::snprintf(out[n].name, sizeof(out[n].name), "%s", kKernelNames[i / 8]);
+        else
+            std::snprintf(out[n].name, sizeof(out[n].name), "%s@L%d", kKernelNames[i / 8], i % 8);
         out[n].launches = c->launches[i];
         out[n].total_ms = c->total_ms[i];
         out[n].voxels = c->voxels[i];
         ++n;
     }
     if (reset)
-        for (int i = 0; i < K_COUNT; ++i) {
+        for (int i = 0; i < K_COUNT * 8; ++i) {
             c->launches[i] = 0;
             c->total_ms[i] = 0.0;
             c->voxels[i] = 0.0;

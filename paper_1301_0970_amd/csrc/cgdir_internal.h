@@ -23,15 +23,18 @@ struct Dims {
 struct ForceArgs {
     const float *I0;          // moving image at this level
     const float *T0;          // target image at this level
-    const uint8_t *mbits;     // bit i = voxel inside structure i on the moving image (or null)
-    const uint8_t *tbits;     // same on the target image (or null)
+    const uint8_t *mbits;     // bit i = voxel inside structure i on the moving image (null: k = 0)
+    const uint8_t *tbits;     // same on the target image
+    const uint8_t *mocc;      // moving-mask occupancy of 8x8x8 bricks (brick_dims)
     const uint8_t *uroi;      // stopping region (or null: no metric)
     const float *u[3];        // current field
     float *du[3];             // output step
     float *partials;          // per-block sums of ((T0 - I0~)/norm)^2 over the UROI
     Dims d;
+    int bnx, bny;             // brick grid x, y extents
     int k;                    // active structures (<= kMaxStructs)
     float lam[kMaxStructs];   // lambda_i
+    float lam_sum;            // lambda_0 + ... + lambda_{k-1}, summed in this order
     float hs[kMaxStructs];    // s_i / 2
     float c0;                 // CT-number offset
     float inv_norm;           // 1 / norm_range
@@ -49,7 +52,8 @@ struct SmoothArgs {
 };
 
 // ---- launchers (cgdir_kernels.hip); each returns the hipError_t of its launch -------
-hipError_t launch_force(const ForceArgs &a, int kp, int ty, hipStream_t s, int *blocks_out);
+hipError_t launch_force(const ForceArgs &a, int ty, hipStream_t s, int *blocks_out);
+hipError_t launch_brick_occupancy(const uint8_t *bits, Dims d, uint8_t *occ, hipStream_t s);
 hipError_t launch_smooth(const SmoothArgs &a, int radius, bool compose, int ty, hipStream_t s);
 hipError_t launch_delta_finalize(const float *partials, int nblocks, const int64_t *count,
                                  double *out, float inv_dummy, hipStream_t s);
@@ -76,5 +80,8 @@ hipError_t launch_dilate_bit(const uint8_t *bits, int bit, Dims d, const int mar
                              uint8_t *rowdist, uint8_t *out, hipStream_t s);
 
 int force_partial_blocks(Dims d, int ty, int tz);
+
+// brick grid of the mask occupancy map (8x8x8 voxels per brick)
+inline Dims brick_dims(Dims d) { return Dims{(d.nx + 7) / 8, (d.ny + 7) / 8, (d.nz + 7) / 8}; }
 
 }  // namespace cgdir

@@ -98,118 +98,229 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// XCD-aware block order.  The dispatcher hands consecutive block ids to the 8 XCDs in
+// turn; the blocks one XCD receives are mapped onto a contiguous range of logical tiles, so
+// that tiles sharing halo cache lines run on the same L2.  Logical order: z chunk fastest,
+// then x tile, then y tile.  Bijective on [0, total).
+__device__ __forceinline__ int xcd_logical(int b, int total)
+{
+    const int per = total >> 3, rem = total & 7;
+    const int x = b & 7, local = b >> 3;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + local;
+}
+
+struct TileCoord {
+    int x0, y0, z0, z1;
+};
+
+__device__ __forceinline__ TileCoord tile_of(int ty_rows, int tz, const Dims &d)
+{
+    const int ntx = (d.nx + kTileX - 1) / kTileX, nty = (d.ny + ty_rows - 1) / ty_rows;
+    const int nzc = (d.nz + tz - 1) / tz;
+    const int L = xcd_logical(blockIdx.x, ntx * nty * nzc);
+    const int zc = L % nzc, t = L / nzc;
+    TileCoord c;
+    c.x0 = (t % ntx) * kTileX;
+    c.y0 = (t / ntx) * ty_rows;
+    c.z0 = zc * tz;
+    c.z1 = min(c.z0 + tz, d.nz);
+    return c;
+}
+
+// Warp of the masked moving image m_i (I0 + c0) at voxel (px, py, pz): K_i~ of the
+// decomposition below, for the structures selected by `bit`.
+__device__ __forceinline__ float warp_masked(const ForceArgs &a, int px, int py, int pz, uint32_t bit)
+{
+    const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
+    const int v = px + nx * py + nxy * pz;
+    const Corners q = corners(split_axis(px, a.u[0][v], nx), split_axis(py, a.u[1][v], ny),
+                              split_axis(pz, a.u[2][v], nz), nx, nxy);
+    const int o[8] = {q.r00 + q.x0, q.r00 + q.x1, q.r10 + q.x0, q.r10 + q.x1,
+                      q.r01 + q.x0, q.r01 + q.x1, q.r11 + q.x0, q.r11 + q.x1};
+    float h[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = (a.mbits[o[j]] & bit) ? a.I0[o[j]] + a.c0 : 0.f;
+    return lerp8(h, q.tx, q.ty, q.tz);
+}
+
 // ============================================================================
 // Force: kernels 2 (gradient), 3 (moving vector, Eq.7) and the image half of kernel 4
 // (warp) fused.  A block owns a 64 x TY column tile and marches through a chunk of z
-// planes.  The warped moving image I0~ = I0(x + u) and the warped masked images
-// K_i~ = (m_i (I0 + c0))(x + u) of each plane (tile + 1-voxel halo) go to a 3-plane LDS
-// ring, from which the central differences are taken.  With s_i the sign of structure i
-// (M_i = s_i m_i, N_i = s_i n_i), the modified images of Eq.2 decompose exactly as
-//   I_i~ = (I0~ + c0) + s_i/2 K_i~,  grad I_i~ = grad I0~ + s_i/2 grad K_i~,
-//   T_i - I_i~ = (T0 - I0~) + s_i/2 (n_i (T0 + c0) - K_i~),
-// so only the mask bits are stored, never the modified images.  Where neither mask of
-// structure i touches the stencil, K_i~ = n_i = 0 and its terms reduce to
-// lambda_i a0 d (numerator) and lambda_i a0^2 (denominator).
+// planes; the warped moving image I0~ = I0(x + u) of each plane (tile + 1-voxel halo)
+// goes to a 3-plane LDS ring from which the central differences are taken, together with
+// a flag telling whether any corner of the cell's trilinear stencil lies inside a moving
+// structure (looked up first in a coarse brick occupancy map, so that most cells never
+// touch the mask bits).
+//
+// With s_i the sign of structure i (M_i = s_i m_i, N_i = s_i n_i), the modified images of
+// Eq.2 decompose exactly (trilinear interpolation and central differences are linear):
+//   I_i~ = (I0~ + c0) + s_i/2 K_i~,   grad I_i~ = grad I0~ + s_i/2 grad K_i~,
+//   T_i - I_i~ = (T0 - I0~) + s_i/2 (n_i (T0 + c0) - K_i~),   K_i~ = (m_i (I0 + c0)) o (Id + u).
+// Where neither mask of structure i touches the stencil, K_i~ = n_i = 0 and its terms of
+// Eq.7 reduce to lambda_i a0 d (numerator) and lambda_i a0^2 (denominator): that is the
+// whole computation for most voxels.  Near a structure, K_i~ is evaluated at the 7 stencil
+// points directly from global memory.
 // ============================================================================
-template <int KP, int TY>
+template <int TY>
 __global__ void __launch_bounds__(kTileX *TY) k_force(ForceArgs a)
 {
-    constexpr int TXH = kTileX + 2, TYH = TY + 2, CELLS = TXH * TYH, NT = kTileX * TY;
-    constexpr int KB_CELLS = KP > 0 ? CELLS : 1;
-    __shared__ float W[3][KP + 1][CELLS];
-    __shared__ uint8_t KB[3][KB_CELLS];
+    constexpr int TXH = kTileX + 2, CELLS = TXH * (TY + 2), NT = kTileX * TY;
+    constexpr int NP = (CELLS + NT - 1) / NT;  // cells per thread and plane
+    __shared__ float W[4][CELLS];               // ring of warped planes, slot (p - z0 + 1) & 3
+    __shared__ float K[4][CELLS];               // K_i~ of the cell's structure when exactly one
+    __shared__ uint8_t F[4][CELLS];             // structures touching the cell's stencil
     __shared__ float red[NT / 64];
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
-    const int ntx = (nx + kTileX - 1) / kTileX;
-    const int x0 = (blockIdx.x % ntx) * kTileX, y0 = (blockIdx.x / ntx) * TY;
-    const int z0 = blockIdx.y * a.tz, z1 = min(z0 + a.tz, nz);
+    const TileCoord tc = tile_of(TY, a.tz, a.d);
+    const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
+    const bool masked = a.mbits != nullptr;
 
     const float *__restrict__ I0 = a.I0;
     const float *__restrict__ ux = a.u[0];
     const float *__restrict__ uy = a.u[1];
     const float *__restrict__ uz = a.u[2];
 
-    // warped values of plane p (index clamped) into ring slot (p - z0 + 1) % 3
-    auto plane = [&](int p) {
+    // the cells (tile + 1-voxel halo) this thread warps, as clamped volume coordinates
+    int cgx[NP], cgy[NP];
+    bool cval[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int c = tid + j * NT;
+        cval[j] = c < CELLS;
+        const int cy = c / TXH, cx = c - cy * TXH;
+        cgx[j] = clampi(x0 - 1 + cx, 0, nx - 1);
+        cgy[j] = clampi(y0 - 1 + cy, 0, ny - 1);
+    }
+
+    // pipeline registers: u of a plane being prefetched, gathers of a plane in flight
+    float U[NP][3];
+    float G[NP][8];
+    float fr[NP][3];
+    int base[NP][3];
+    uint32_t occ[NP];
+
+    auto load_u = [&](int p) {
         const int pz = clampi(p, 0, nz - 1);
-        const int s = (p - z0 + 1) % 3;
-        for (int c = tid; c < CELLS; c += NT) {
-            const int cy = c / TXH, cx = c - cy * TXH;
-            const int gx = clampi(x0 - 1 + cx, 0, nx - 1);
-            const int gy = clampi(y0 - 1 + cy, 0, ny - 1);
-            const int v = gx + nx * gy + nxy * pz;
-            const Split sx = split_axis(gx, ux[v], nx);
-            const Split sy = split_axis(gy, uy[v], ny);
-            const Split sz = split_axis(pz, uz[v], nz);
-            const Corners q = corners(sx, sy, sz, nx, nxy);
-            float f[8];
-            f[0] = I0[q.r00 + q.x0];
-            f[1] = I0[q.r00 + q.x1];
-            f[2] = I0[q.r10 + q.x0];
-            f[3] = I0[q.r10 + q.x1];
-            f[4] = I0[q.r01 + q.x0];
-            f[5] = I0[q.r01 + q.x1];
-            f[6] = I0[q.r11 + q.x0];
-            f[7] = I0[q.r11 + q.x1];
-            W[s][0][c] = lerp8(f, q.tx, q.ty, q.tz);
-            if constexpr (KP > 0) {
-                const uint8_t *__restrict__ mb = a.mbits;
-                uint32_t b[8];
-                b[0] = mb[q.r00 + q.x0];
-                b[1] = mb[q.r00 + q.x1];
-                b[2] = mb[q.r10 + q.x0];
-                b[3] = mb[q.r10 + q.x1];
-                b[4] = mb[q.r01 + q.x0];
-                b[5] = mb[q.r01 + q.x1];
-                b[6] = mb[q.r11 + q.x0];
-                b[7] = mb[q.r11 + q.x1];
-                const uint32_t any = b[0] | b[1] | b[2] | b[3] | b[4] | b[5] | b[6] | b[7];
-                KB[s][c] = (uint8_t)any;
-                if (any) {
-                    float g[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) g[j] = f[j] + a.c0;
-#pragma unroll
-                    for (int i = 0; i < KP; ++i) {
-                        float kv = 0.f;
-                        if ((any >> i) & 1u) {
-                            float h[8];
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) h[j] = ((b[j] >> i) & 1u) ? g[j] : 0.f;
-                            kv = lerp8(h, q.tx, q.ty, q.tz);
-                        }
-                        W[s][1 + i][c] = kv;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < KP; ++i) W[s][1 + i][c] = 0.f;
-                }
+        for (int j = 0; j < NP; ++j)
+            if (cval[j]) {
+                const int v = cgx[j] + nx * cgy[j] + nxy * pz;
+                U[j][0] = ux[v];
+                U[j][1] = uy[v];
+                U[j][2] = uz[v];
             }
-        }
+    };
+    auto issue_gathers = [&](int p) {
+        const int pz = clampi(p, 0, nz - 1);
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+            if (cval[j]) {
+                const Split sx = split_axis(cgx[j], U[j][0], nx);
+                const Split sy = split_axis(cgy[j], U[j][1], ny);
+                const Split sz = split_axis(pz, U[j][2], nz);
+                const Corners q = corners(sx, sy, sz, nx, nxy);
+                G[j][0] = I0[q.r00 + q.x0];
+                G[j][1] = I0[q.r00 + q.x1];
+                G[j][2] = I0[q.r10 + q.x0];
+                G[j][3] = I0[q.r10 + q.x1];
+                G[j][4] = I0[q.r01 + q.x0];
+                G[j][5] = I0[q.r01 + q.x1];
+                G[j][6] = I0[q.r11 + q.x0];
+                G[j][7] = I0[q.r11 + q.x1];
+                base[j][0] = sx.i0;
+                base[j][1] = sy.i0;
+                base[j][2] = sz.i0;
+                fr[j][0] = q.tx;
+                fr[j][1] = q.ty;
+                fr[j][2] = q.tz;
+                occ[j] = masked ? a.mocc[(sx.i0 >> 3) + a.bnx * ((sy.i0 >> 3) + a.bny * (sz.i0 >> 3))] : 0u;
+            }
+    };
+    auto finish_plane = [&](int p) {
+        const int s = (p - z0 + 1) & 3;
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+            if (cval[j]) {
+                const int c = tid + j * NT;
+                W[s][c] = lerp8(G[j], fr[j][0], fr[j][1], fr[j][2]);
+                uint32_t any = 0;
+                float kv = 0.f;
+                if (occ[j]) {  // a structure is near: mask bits at the 8 corners
+                    const int i0 = base[j][0], j0 = base[j][1], l0 = base[j][2];
+                    const int i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
+                    const uint8_t *__restrict__ mb = a.mbits;
+                    uint32_t b[8];
+                    b[0] = mb[i0 + nx * j0 + nxy * l0];
+                    b[1] = mb[i1 + nx * j0 + nxy * l0];
+                    b[2] = mb[i0 + nx * j1 + nxy * l0];
+                    b[3] = mb[i1 + nx * j1 + nxy * l0];
+                    b[4] = mb[i0 + nx * j0 + nxy * l1];
+                    b[5] = mb[i1 + nx * j0 + nxy * l1];
+                    b[6] = mb[i0 + nx * j1 + nxy * l1];
+                    b[7] = mb[i1 + nx * j1 + nxy * l1];
+                    any = b[0] | b[1] | b[2] | b[3] | b[4] | b[5] | b[6] | b[7];
+                    if (any != 0 && (any & (any - 1)) == 0) {  // one structure: its K_i~ here
+                        float h[8];
+#pragma unroll
+                        for (int m = 0; m < 8; ++m) h[m] = (b[m] & any) ? G[j][m] + a.c0 : 0.f;
+                        kv = lerp8(h, fr[j][0], fr[j][1], fr[j][2]);
+                    }
+                }
+                F[s][c] = (uint8_t)any;
+                K[s][c] = kv;
+            }
     };
 
-    plane(z0 - 1);
-    plane(z0);
-    __syncthreads();
+    // prologue: planes z0 - 1, z0, z0 + 1 warped; u of z0 + 2 and the target row of z0 loaded
+    load_u(z0 - 1);
+    issue_gathers(z0 - 1);
+    finish_plane(z0 - 1);
+    load_u(z0);
+    issue_gathers(z0);
+    finish_plane(z0);
+    load_u(z0 + 1);
+    issue_gathers(z0 + 1);
+    finish_plane(z0 + 1);
+    load_u(z0 + 2);
 
-    float dacc = 0.f;
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < nx && gy < ny;
     const int c = (ty + 1) * TXH + (tx + 1);
+    float t0r = 0.f;
+    uint32_t tbr = 0, urr = 0;
+    auto load_target = [&](int z) {
+        if (own && z < z1) {
+            const int v = gx + nx * gy + nxy * z;
+            t0r = a.T0[v];
+            tbr = masked ? a.tbits[v] : 0u;
+            urr = a.partials != nullptr ? a.uroi[v] : 0u;
+        }
+    };
+    load_target(z0);
+    __syncthreads();
+
+    float dacc = 0.f;
     for (int z = z0; z < z1; ++z) {
-        plane(z + 1);
-        __syncthreads();
+        // (1) gathers of plane z + 2 and the u of plane z + 3 go in flight
+        const bool ahead = z + 2 <= z1;
+        if (ahead) {
+            issue_gathers(z + 2);
+            if (z + 3 <= z1) load_u(z + 3);
+        }
+        // (2) the step of plane z from the ring (planes z - 1, z, z + 1)
         if (own) {
             const int v = gx + nx * gy + nxy * z;
-            const int sm = (z - z0) % 3, s0 = (z - z0 + 1) % 3, sp = (z - z0 + 2) % 3;
-            const float Ic = W[s0][0][c];
-            const float g0x = 0.5f * (W[s0][0][c + 1] - W[s0][0][c - 1]);
-            const float g0y = 0.5f * (W[s0][0][c + TXH] - W[s0][0][c - TXH]);
-            const float g0z = 0.5f * (W[sp][0][c] - W[sm][0][c]);
-            const float t0 = a.T0[v];
+            const int sm = (z - z0) & 3, s0 = (z - z0 + 1) & 3, sp = (z - z0 + 2) & 3;
+            const float Ic = W[s0][c];
+            const float g0x = 0.5f * (W[s0][c + 1] - W[s0][c - 1]);
+            const float g0y = 0.5f * (W[s0][c + TXH] - W[s0][c - TXH]);
+            const float g0z = 0.5f * (W[sp][c] - W[sm][c]);
+            const float t0 = t0r;
+            const uint32_t tb = tbr;
+            const bool in_uroi = urr != 0;
             const float d = t0 - Ic;
             const float a02 = __builtin_fmaf(g0z, g0z, __builtin_fmaf(g0y, g0y, g0x * g0x));
             float dx = 0.f, dy = 0.f, dz = 0.f;
@@ -219,25 +330,58 @@ __global__ void __launch_bounds__(kTileX *TY) k_force(ForceArgs a)
                 const float nxv = g0x * inv, nyv = g0y * inv, nzv = g0z * inv;
                 float num = a0 * d;
                 float den = __builtin_fmaf(d, d, a02);  // beta = d^2 (Thirion)
-                if constexpr (KP > 0) {
-                    const uint32_t tb = a.tbits[v];
-                    const uint32_t kb = (uint32_t)KB[s0][c] | KB[s0][c - 1] | KB[s0][c + 1] |
-                                        KB[s0][c - TXH] | KB[s0][c + TXH] | KB[sm][c] | KB[sp][c] | tb;
-                    const float tc = t0 + a.c0;
-                    float lam_off = 0.f;
-#pragma unroll
-                    for (int i = 0; i < KP; ++i) {
-                        if (i < a.k) {
-                            if ((kb >> i) & 1u) {
-                                const float *Wi0 = W[s0][1 + i];
-                                const float Kc = Wi0[c];
-                                const float gkx = 0.5f * (Wi0[c + 1] - Wi0[c - 1]);
-                                const float gky = 0.5f * (Wi0[c + TXH] - Wi0[c - TXH]);
-                                const float gkz = 0.5f * (W[sp][1 + i][c] - W[sm][1 + i][c]);
-                                const float proj =
-                                    __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
+                float lam_off = a.lam_sum;
+                if (masked) {
+                    const uint32_t kb = (uint32_t)F[s0][c] | F[s0][c - 1] | F[s0][c + 1] | F[s0][c - TXH] |
+                                        F[s0][c + TXH] | F[sm][c] | F[sp][c] | tb;
+                    if (kb != 0 && (kb & (kb - 1)) == 0) {
+                        // one structure i near: every stencil cell holds K_i~ (0 where its
+                        // corners miss the structure), so its terms come from the ring
+                        const int i = __builtin_ctz(kb);
+                        const float Kc = K[s0][c];
+                        const float gkx = 0.5f * (K[s0][c + 1] - K[s0][c - 1]);
+                        const float gky = 0.5f * (K[s0][c + TXH] - K[s0][c - TXH]);
+                        const float gkz = 0.5f * (K[sp][c] - K[sm][c]);
+                        const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
+                        const float ai = __builtin_fmaf(a.hs[i], proj, a0);
+                        const float ni = (tb & kb) ? t0 + a.c0 : 0.f;
+                        const float di = __builtin_fmaf(a.hs[i], ni - Kc, d);
+                        const float la = a.lam[i] * ai;
+                        num = __builtin_fmaf(la, di, num);
+                        den = __builtin_fmaf(la, ai, den);
+                        lam_off = 0.f;
+                        for (int j = 0; j < a.k; ++j)
+                            if (j != i) lam_off += a.lam[j];
+                    } else if (kb) {  // several structures near: their terms in full
+                        lam_off = 0.f;
+                        const float tc0 = t0 + a.c0;
+                        const int xm = max(gx - 1, 0), xp = min(gx + 1, nx - 1);
+                        const int ym = max(gy - 1, 0), yp = min(gy + 1, ny - 1);
+                        const int zm = max(z - 1, 0), zp = min(z + 1, nz - 1);
+#pragma unroll 1
+                        for (int i = 0; i < a.k; ++i) {
+                            const uint32_t bit = 1u << i;
+                            if (kb & bit) {
+                                // K_i~ at the centre and the six clamped neighbours
+                                float Kc = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
+#pragma unroll 1
+                                for (int q = 0; q < 7; ++q) {
+                                    const int px = q == 1 ? xp : (q == 2 ? xm : gx);
+                                    const int py = q == 3 ? yp : (q == 4 ? ym : gy);
+                                    const int pz = q == 5 ? zp : (q == 6 ? zm : z);
+                                    const float K = warp_masked(a, px, py, pz, bit);
+                                    const float hK = 0.5f * K;
+                                    if (q == 0) Kc = K;
+                                    else if (q == 1) gkx = hK;
+                                    else if (q == 2) gkx -= hK;
+                                    else if (q == 3) gky = hK;
+                                    else if (q == 4) gky -= hK;
+                                    else if (q == 5) gkz = hK;
+                                    else gkz -= hK;
+                                }
+                                const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
                                 const float ai = __builtin_fmaf(a.hs[i], proj, a0);
-                                const float ni = ((tb >> i) & 1u) ? tc : 0.f;
+                                const float ni = (tb & bit) ? tc0 : 0.f;
                                 const float di = __builtin_fmaf(a.hs[i], ni - Kc, d);
                                 const float la = a.lam[i] * ai;
                                 num = __builtin_fmaf(la, di, num);
@@ -247,9 +391,9 @@ __global__ void __launch_bounds__(kTileX *TY) k_force(ForceArgs a)
                             }
                         }
                     }
-                    num = __builtin_fmaf(lam_off * a0, d, num);
-                    den = __builtin_fmaf(lam_off, a02, den);
                 }
+                num = __builtin_fmaf(lam_off * a0, d, num);
+                den = __builtin_fmaf(lam_off, a02, den);
                 const float vv = num / den;
                 dx = vv * nxv;
                 dy = vv * nyv;
@@ -258,11 +402,14 @@ __global__ void __launch_bounds__(kTileX *TY) k_force(ForceArgs a)
             a.du[0][v] = dx;
             a.du[1][v] = dy;
             a.du[2][v] = dz;
-            if (a.partials != nullptr && a.uroi[v]) {
+            if (in_uroi) {
                 const float e = d * a.inv_norm;
                 dacc = __builtin_fmaf(e, e, dacc);
             }
         }
+        // (3) the target row of plane z + 1, then the warped plane z + 2 into the ring
+        load_target(z + 1);
+        if (ahead) finish_plane(z + 2);
         __syncthreads();
     }
 
@@ -274,9 +421,26 @@ __global__ void __launch_bounds__(kTileX *TY) k_force(ForceArgs a)
             float s = 0.f;
 #pragma unroll
             for (int w = 0; w < NT / 64; ++w) s += red[w];
-            a.partials[blockIdx.x + gridDim.x * blockIdx.y] = s;
+            a.partials[blockIdx.x] = s;
         }
     }
+}
+
+// Moving-mask occupancy of 8x8x8 bricks: OR of the mask bits over the brick grown by one
+// voxel on its high side, so that a trilinear stencil whose base corner lies in the brick
+// touches a structure only if the brick's entry is nonzero.
+__global__ void __launch_bounds__(256) k_brick_occupancy(const uint8_t *__restrict__ bits, Dims d, Dims db,
+                                                         uint8_t *__restrict__ occ)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= db.n()) return;
+    const int bx = (int)(b % db.nx), by = (int)((b / db.nx) % db.ny), bz = (int)(b / ((int64_t)db.nx * db.ny));
+    uint32_t o = 0;
+    for (int l = 8 * bz; l <= min(8 * bz + 8, d.nz - 1); ++l)
+        for (int j = 8 * by; j <= min(8 * by + 8, d.ny - 1); ++j)
+            for (int i = 8 * bx; i <= min(8 * bx + 8, d.nx - 1); ++i)
+                o |= bits[i + (int64_t)d.nx * (j + (int64_t)d.ny * l)];
+    occ[b] = (uint8_t)o;
 }
 
 // ============================================================================
@@ -290,15 +454,18 @@ template <int R, int TY, bool COMPOSE>
 __global__ void __launch_bounds__(kTileX *TY) k_smooth(SmoothArgs a)
 {
     constexpr int WD = kTileX + 2 * R, HT = TY + 2 * R, NT = kTileX * TY;
+    constexpr int CELLS = HT * WD, NP = (CELLS + NT - 1) / NT;
+    constexpr int UW = kTileX + 2, UH = TY + 2, UCELLS = UW * UH, NU = (UCELLS + NT - 1) / NT;
+    constexpr int US = COMPOSE ? 3 : 1;
     __shared__ float raw[3][HT][WD];
     __shared__ float xs[3][HT][kTileX];
+    __shared__ float Us[3][US][COMPOSE ? UCELLS : 1];  // compose: u planes z-1..z+1, ring slot (p - z0 + 1) % 3
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
-    const int ntx = (nx + kTileX - 1) / kTileX;
-    const int x0 = (blockIdx.x % ntx) * kTileX, y0 = (blockIdx.x / ntx) * TY;
-    const int z0 = blockIdx.y * a.tz, z1 = min(z0 + a.tz, nz);
+    const TileCoord tc = tile_of(TY, a.tz, a.d);
+    const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
     float w[R + 1];
 #pragma unroll
     for (int m = 0; m <= R; ++m) w[m] = a.w[m];
@@ -307,17 +474,81 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth(SmoothArgs a)
     const float *__restrict__ in1 = a.in[1];
     const float *__restrict__ in2 = a.in[2];
 
-    auto plane = [&](int p, float out[3]) {
-        const int pz = clampi(p, 0, nz - 1);
-        for (int c = tid; c < HT * WD; c += NT) {
-            const int r = c / WD, q = c - r * WD;
-            const int gx = clampi(x0 - R + q, 0, nx - 1);
-            const int gy = clampi(y0 - R + r, 0, ny - 1);
-            const int v = gx + nx * gy + nxy * pz;
-            raw[0][r][q] = in0[v];
-            raw[1][r][q] = in1[v];
-            raw[2][r][q] = in2[v];
+    // staged cells of this thread (tile + R halo), as clamped in-plane offsets
+    int coff[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int c = tid + j * NT;
+        const int r = c / WD, q = c - r * WD;
+        coff[j] = clampi(x0 - R + q, 0, nx - 1) + nx * clampi(y0 - R + r, 0, ny - 1);
+    }
+    // the next plane's staged values are prefetched into registers while the current
+    // plane is filtered
+    float pre[NP][3];
+    auto prefetch = [&](int p) {
+        const int base = nxy * clampi(p, 0, nz - 1);
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+            if (tid + j * NT < CELLS) {
+                pre[j][0] = in0[base + coff[j]];
+                pre[j][1] = in1[base + coff[j]];
+                pre[j][2] = in2[base + coff[j]];
+            }
+    };
+
+    // compose: the field's planes around the output plane, tile + 1-voxel halo
+    int uoff[NU];
+    float upre[NU][3];
+    if constexpr (COMPOSE) {
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const int c = tid + j * NT;
+            const int r = c / UW, q = c - r * UW;
+            uoff[j] = clampi(x0 - 1 + q, 0, nx - 1) + nx * clampi(y0 - 1 + r, 0, ny - 1);
         }
+    }
+    auto u_load = [&](int p) {
+        if constexpr (COMPOSE) {
+            const int base = nxy * clampi(p, 0, nz - 1);
+#pragma unroll
+            for (int j = 0; j < NU; ++j)
+                if (tid + j * NT < UCELLS) {
+                    upre[j][0] = a.u[0][base + uoff[j]];
+                    upre[j][1] = a.u[1][base + uoff[j]];
+                    upre[j][2] = a.u[2][base + uoff[j]];
+                }
+        }
+    };
+    auto u_store = [&](int p) {
+        if constexpr (COMPOSE) {
+            const int sl = (p - z0 + 1) % 3;
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                const int c = tid + j * NT;
+                if (c < UCELLS) {
+                    Us[0][sl][c] = upre[j][0];
+                    Us[1][sl][c] = upre[j][1];
+                    Us[2][sl][c] = upre[j][2];
+                }
+            }
+        }
+    };
+
+    // x then y pass of the plane held in `pre`; `p1` is prefetched meanwhile.  In compose
+    // mode the u plane `ustore` (loaded earlier) goes into its ring slot and u plane
+    // `uload` is loaded.
+    auto filter_plane = [&](int p1, bool more, int ustore, int uload, float out[3]) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int c = tid + j * NT;
+            if (c < CELLS) {
+                const int r = c / WD, q = c - r * WD;
+                raw[0][r][q] = pre[j][0];
+                raw[1][r][q] = pre[j][1];
+                raw[2][r][q] = pre[j][2];
+            }
+        }
+        if (more) prefetch(p1);
         __syncthreads();
         for (int c = tid; c < HT * kTileX; c += NT) {
             const int r = c / kTileX, q = c - r * kTileX;
@@ -328,6 +559,10 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth(SmoothArgs a)
                 for (int m = 1; m <= R; ++m) s = __builtin_fmaf(w[m], raw[k][r][q + R - m] + raw[k][r][q + R + m], s);
                 xs[k][r][q] = s;
             }
+        }
+        if (ustore >= 0) {
+            u_store(ustore);
+            if (uload >= 0) u_load(uload);
         }
         __syncthreads();
 #pragma unroll
@@ -354,14 +589,22 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth(SmoothArgs a)
     };
 
     float v3[3];
+    if constexpr (COMPOSE) {  // u planes z0 - 1 and z0 into the ring, z0 + 1 into registers
+        u_load(z0 - 1);
+        u_store(z0 - 1);
+        u_load(z0);
+        u_store(z0);
+        u_load(z0 + 1);
+    }
+    prefetch(z0 - R);
     for (int q = 0; q < 2 * R; ++q) {
-        plane(z0 - R + q, v3);
+        filter_plane(z0 - R + q + 1, true, -1, -1, v3);
         push(v3);
     }
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < nx && gy < ny;
     for (int z = z0; z < z1; ++z) {
-        plane(z + R, v3);
+        filter_plane(z + R + 1, z + 1 < z1, COMPOSE ? z + 1 : -1, z + 2 <= z1 ? z + 2 : -1, v3);
         push(v3);
         if (own) {
             const int v = gx + nx * gy + nxy * z;
@@ -377,9 +620,30 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth(SmoothArgs a)
                 const Split sx = split_axis(gx, s[0], nx);
                 const Split sy = split_axis(gy, s[1], ny);
                 const Split sz = split_axis(z, s[2], nz);
-                const Corners q = corners(sx, sy, sz, nx, nxy);
+                const bool near = sx.i0 >= gx - 1 && sx.i1 <= gx + 1 && sy.i0 >= gy - 1 && sy.i1 <= gy + 1 &&
+                                  sz.i0 >= z - 1 && sz.i1 <= z + 1;
+                if (near) {  // all corners in the staged planes
+                    const int cx0 = sx.i0 - (x0 - 1), cx1 = sx.i1 - (x0 - 1);
+                    const int ry0 = (sy.i0 - (y0 - 1)) * UW, ry1 = (sy.i1 - (y0 - 1)) * UW;
+                    const int sl0 = (sz.i0 - z0 + 1) % 3, sl1 = (sz.i1 - z0 + 1) % 3;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) a.out[k][v] = s[k] + trilinear(a.u[k], q);
+                    for (int k = 0; k < 3; ++k) {
+                        float f[8];
+                        f[0] = Us[k][sl0][ry0 + cx0];
+                        f[1] = Us[k][sl0][ry0 + cx1];
+                        f[2] = Us[k][sl0][ry1 + cx0];
+                        f[3] = Us[k][sl0][ry1 + cx1];
+                        f[4] = Us[k][sl1][ry0 + cx0];
+                        f[5] = Us[k][sl1][ry0 + cx1];
+                        f[6] = Us[k][sl1][ry1 + cx0];
+                        f[7] = Us[k][sl1][ry1 + cx1];
+                        a.out[k][v] = s[k] + lerp8(f, sx.t, sy.t, sz.t);
+                    }
+                } else {
+                    const Corners q = corners(sx, sy, sz, nx, nxy);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) a.out[k][v] = s[k] + trilinear(a.u[k], q);
+                }
             } else {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) a.out[k][v] = s[k];
@@ -668,41 +932,35 @@ static int tiles_xy(Dims d, int ty) { return ((d.nx + kTileX - 1) / kTileX) * ((
 
 int force_partial_blocks(Dims d, int ty, int tz) { return tiles_xy(d, ty) * ((d.nz + tz - 1) / tz); }
 
-template <int KP, int TY>
-static hipError_t force_kp_ty(const ForceArgs &a, hipStream_t s)
+template <int TY>
+static hipError_t force_ty(const ForceArgs &a, hipStream_t s)
 {
-    dim3 grid(tiles_xy(a.d, TY), (a.d.nz + a.tz - 1) / a.tz);
-    hipLaunchKernelGGL((k_force<KP, TY>), grid, dim3(kTileX * TY), 0, s, a);
+    hipLaunchKernelGGL((k_force<TY>), dim3(force_partial_blocks(a.d, TY, a.tz)), dim3(kTileX * TY), 0, s, a);
     return hipGetLastError();
 }
 
-template <int TY>
-static hipError_t force_ty(const ForceArgs &a, int kp, hipStream_t s)
+hipError_t launch_force(const ForceArgs &a, int ty, hipStream_t s, int *blocks_out)
 {
-    switch (kp) {
-    case 0: return force_kp_ty<0, TY>(a, s);
-    case 1: return force_kp_ty<1, TY>(a, s);
-    case 2: return force_kp_ty<2, TY>(a, s);
-    case 4: return force_kp_ty<4, TY>(a, s);
-    case 8: return force_kp_ty<8, TY>(a, s);
+    if (blocks_out) *blocks_out = force_partial_blocks(a.d, ty, a.tz);
+    switch (ty) {
+    case 4: return force_ty<4>(a, s);
+    case 8: return force_ty<8>(a, s);
+    case 16: return force_ty<16>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_force(const ForceArgs &a, int kp, int ty, hipStream_t s, int *blocks_out)
+hipError_t launch_brick_occupancy(const uint8_t *bits, Dims d, uint8_t *occ, hipStream_t s)
 {
-    if (blocks_out) *blocks_out = force_partial_blocks(a.d, ty, a.tz);
-    switch (ty) {
-    case 4: return force_ty<4>(a, kp, s);
-    case 8: return force_ty<8>(a, kp, s);
-    default: return hipErrorInvalidValue;
-    }
+    const Dims db = brick_dims(d);
+    hipLaunchKernelGGL(k_brick_occupancy, dim3(blocks_for(db.n(), 256)), dim3(256), 0, s, bits, d, db, occ);
+    return hipGetLastError();
 }
 
 template <int R, int TY>
 static hipError_t smooth_r_ty(const SmoothArgs &a, bool compose, hipStream_t s)
 {
-    dim3 grid(tiles_xy(a.d, TY), (a.d.nz + a.tz - 1) / a.tz);
+    dim3 grid(tiles_xy(a.d, TY) * ((a.d.nz + a.tz - 1) / a.tz));
     if (compose)
         hipLaunchKernelGGL((k_smooth<R, TY, true>), grid, dim3(kTileX * TY), 0, s, a);
     else
@@ -730,6 +988,7 @@ hipError_t launch_smooth(const SmoothArgs &a, int radius, bool compose, int ty, 
     switch (ty) {
     case 4: return smooth_ty<4>(a, radius, compose, s);
     case 8: return smooth_ty<8>(a, radius, compose, s);
+    case 16: return smooth_ty<16>(a, radius, compose, s);
     default: return hipErrorInvalidValue;
     }
 }

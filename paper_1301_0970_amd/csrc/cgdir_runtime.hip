@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -124,8 +125,6 @@ void gauss_taps(float sigma, float *w)
     for (int m = 0; m <= R; ++m) w[m] = (float)(t[m] / sum);
 }
 
-int kp_for(int k) { return k == 0 ? 0 : (k == 1 ? 1 : (k == 2 ? 2 : (k <= 4 ? 4 : 8))); }
-
 Dims level_dims(Dims d0, int l)
 {
     Dims d = d0;
@@ -139,9 +138,24 @@ Dims level_dims(Dims d0, int l)
 
 // launch geometry (tile rows, z planes per block) of the iteration kernels
 struct Tuning {
-    int force_ty = 4, force_tz = 16;
+    int force_ty = 4, force_tz = 8;
     int smooth_ty = 8, smooth_tz = 32;
 };
+
+// CGDIR_TUNE="force_ty,force_tz,smooth_ty,smooth_tz" overrides the launch geometry
+Tuning tuning_from_env()
+{
+    Tuning t;
+    const char *e = std::getenv("CGDIR_TUNE");
+    if (e) {
+        int a, b, c, d;
+        if (std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d) == 4) {
+            auto ty_ok = [](int v) { return v == 4 || v == 8 || v == 16; };
+            if (ty_ok(a) && b >= 1 && ty_ok(c) && d >= 1) t = Tuning{a, b, c, d};
+        }
+    }
+    return t;
+}
 
 bool want_delta(const cgdir_params &p) { return p.stop_mode != 0 || p.delta_hist != nullptr; }
 
@@ -152,7 +166,7 @@ size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, 
     b += 3 * align_up(3 * n0 * sizeof(float));  // u, du, uc
     for (int l = 1; l < p.levels; ++l) b += 2 * align_up((size_t)level_dims(d0, l).n() * sizeof(float));
     if (host_images) b += 2 * align_up(n0 * sizeof(float));
-    if (k > 0) b += 2 * align_up(n0);  // bit-planes
+    if (k > 0) b += 2 * align_up(n0) + align_up((size_t)brick_dims(d0).n());  // bit-planes, occupancy
     if (want_delta(p)) {
         b += align_up(n0);  // UROI
         b += align_up((size_t)force_partial_blocks(d0, t.force_ty, t.force_tz) * sizeof(float));
@@ -362,7 +376,7 @@ struct Job {
 
     std::vector<void *> allocs;
     const float *I0[CGDIR_MAX_LEVELS] = {}, *T0[CGDIR_MAX_LEVELS] = {};
-    uint8_t *mbits = nullptr, *tbits = nullptr, *uroi = nullptr;
+    uint8_t *mbits = nullptr, *tbits = nullptr, *uroi = nullptr, *mocc = nullptr;
     float *ubuf = nullptr, *dubuf = nullptr, *ucbuf = nullptr;
     float *partials = nullptr;
     double *delta_dev = nullptr;
@@ -454,7 +468,8 @@ struct Job {
         if (k > 0) {
             mbits = (uint8_t *)take(n0);
             tbits = (uint8_t *)take(n0);
-            ok = ok && mbits && tbits;
+            mocc = (uint8_t *)take((size_t)brick_dims(d0).n());
+            ok = ok && mbits && tbits && mocc;
         }
         if (delta_on) {
             uroi = (uint8_t *)take(n0);
@@ -506,6 +521,7 @@ struct Job {
                 HIP_TRY(timed(ctx, K_PACK * 8 + 7, (double)n0, [&] { return launch_pack_masks(planes, k, n0, bits, s); }));
                 if (m.where == CGDIR_HOST) HIP_TRY(hipStreamSynchronize(s));  // staging reused next side
             }
+            HIP_TRY(timed(ctx, K_PACK * 8 + 7, (double)n0, [&] { return launch_brick_occupancy(mbits, d0, mocc, s); }));
         }
         uint8_t *rowdist = (uint8_t *)dubuf;  // scratch during setup
         if (delta_on) {
@@ -594,6 +610,10 @@ struct Job {
         fa.T0 = T0[level];
         fa.mbits = contour ? mbits : nullptr;
         fa.tbits = contour ? tbits : nullptr;
+        fa.mocc = contour ? mocc : nullptr;
+        const Dims db = brick_dims(d);
+        fa.bnx = db.nx;
+        fa.bny = db.ny;
         fa.uroi = metric ? uroi : nullptr;
         fa.partials = metric ? partials : nullptr;
         for (int c = 0; c < 3; ++c) {
@@ -602,16 +622,17 @@ struct Job {
         }
         fa.d = d;
         fa.k = contour ? k : 0;
+        fa.lam_sum = 0.f;
         for (int i = 0; i < kMaxStructs; ++i) {
             fa.lam[i] = i < k ? lam[i] : 0.f;
             fa.hs[i] = i < k ? hs[i] : 0.f;
+            if (i < fa.k) fa.lam_sum += fa.lam[i];
         }
         fa.c0 = req.params.intensity_offset;
         fa.inv_norm = 1.0f / req.params.norm_range;
         fa.tz = ctx->tune.force_tz;
         int nblocks = 0;
-        const int kp = kp_for(fa.k);
-        HIP_TRY(timed(ctx, K_FORCE * 8 + level, (double)d.n(), [&] { return launch_force(fa, kp, ctx->tune.force_ty, s, &nblocks); }));
+        HIP_TRY(timed(ctx, K_FORCE * 8 + level, (double)d.n(), [&] { return launch_force(fa, ctx->tune.force_ty, s, &nblocks); }));
         if (metric)
             HIP_TRY(timed(ctx, K_DELTA * 8 + level, 0.0, [&] {
                 return launch_delta_finalize(partials, nblocks, misc_i64, delta_dev + iter, 0.f, s);
@@ -920,6 +941,7 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
     c->device = desc->device;
     c->max_slots = desc->max_slots;
     c->profile = (desc->flags & CGDIR_CTX_PROFILE) != 0;
+    c->tune = tuning_from_env();
     if (desc->stream) {
         c->stream = (hipStream_t)desc->stream;
     } else {

@@ -132,6 +132,40 @@ def served(ctx_cls, cgdir, P, torch, duration, rate, pool_bytes, distinct):
             "serial_ms_per_registration": serial_s * 1e3, "distinct_pairs": len(items)}
 
 
+def batched(cgdir, P, torch, n_pairs):
+    """The uneven batch (sizes and structure counts drawn per pair): all pairs in one
+    cgdir_register_batch call vs the same pairs registered one at a time."""
+    specs = P.batch_specs(n_pairs)
+    pairs = [P.from_spec(s) for s in specs]
+    dev = torch.device("cuda")
+    items = [(torch.from_numpy(p.target).to(dev), torch.from_numpy(p.moving).to(dev),
+              torch.from_numpy(p.target_masks).to(dev), torch.from_numpy(p.moving_masks).to(dev))
+             for p in pairs]
+    prms = [cgdir.params_for_pair(p) for p in pairs]
+    outs = [torch.empty((3,) + p.target.shape, device=dev) for p in pairs]
+    vi = sum(p.voxel_iterations() for p in pairs)
+    pool = sum(cgdir.footprint(*p.dims, p.k, pr) for p, pr in zip(pairs, prms)) + (256 << 20)
+    with cgdir.Context(pool) as ctx:
+        ctx.register(*items[0], prms[0], outs[0])      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it, pr, o in zip(items, prms, outs):
+            ctx.register(*it, pr, o)
+        torch.cuda.synchronize()
+        serial = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rc, st = ctx.register_batch(items, prms, outs)
+        torch.cuda.synchronize()
+        batch = time.perf_counter() - t0
+        if rc != cgdir.OK:
+            raise RuntimeError("batch failed: %s" % cgdir.strerror(rc))
+    return {"pairs": n_pairs, "voxel_iterations": vi,
+            "batched_value": vi / batch, "batched_ms": batch * 1e3,
+            "one_at_a_time_value": vi / serial, "one_at_a_time_ms": serial * 1e3,
+            "speedup": serial / batch, "unit": "voxel-iter/s",
+            "sizes": [list(p.dims) for p in pairs], "structures": [p.k for p in pairs]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +174,8 @@ def main():
     ap.add_argument("--workload", default="pelvis", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="also run the served workload")
+    ap.add_argument("--batch", type=int, default=0, metavar="PAIRS",
+                    help="also run the uneven batched workload with this many pairs (32 in full)")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates HBM byte counters)")
@@ -234,6 +270,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(pair)
+    if args.batch:
+        log("batched workload")
+        result["batched"] = batched(cgdir, P, torch, args.batch)
     if args.serve:
         log("served workload")
         result["served"] = served(cgdir.Context, cgdir, P, torch, args.serve_seconds, 4.0,

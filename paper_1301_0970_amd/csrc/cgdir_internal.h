@@ -51,12 +51,41 @@ struct SmoothArgs {
     int tz;
 };
 
+// One pair's stopping-metric reduction in a batched finalize.
+struct DeltaJob {
+    const float *partials;
+    int nblocks;
+    const int64_t *count;
+    double *out;
+};
+
+// Batched launches: one launch over the tiles of n pairs.  The descriptors travel in the
+// kernel-argument segment (<= 4 KiB), so a launch holds a bounded number of pairs.
+// prefix[q] = first block of pair q, prefix[n] = total blocks.
+constexpr int kBatchForce = 16, kBatchSmooth = 24, kBatchDelta = 64;
+struct ForceBatch {
+    int n;
+    int prefix[kBatchForce + 1];
+    ForceArgs d[kBatchForce];
+};
+struct SmoothBatch {
+    int n;
+    int prefix[kBatchSmooth + 1];
+    SmoothArgs d[kBatchSmooth];
+};
+struct DeltaBatch {
+    int n;
+    DeltaJob d[kBatchDelta];
+};
+static_assert(sizeof(ForceBatch) <= 4096 && sizeof(SmoothBatch) <= 4096 && sizeof(DeltaBatch) <= 4096,
+              "kernel arguments are limited to 4 KiB");
+
 // ---- launchers (cgdir_kernels.hip); each returns the hipError_t of its launch -------
-hipError_t launch_force(const ForceArgs &a, int ty, hipStream_t s, int *blocks_out);
+hipError_t launch_force_batch(const ForceBatch &b, int ty, hipStream_t s);
+hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, bool compose, int ty, hipStream_t s);
+hipError_t launch_delta_batch(const DeltaBatch &b, hipStream_t s);
+int tile_blocks(Dims d, int ty, int tz);
 hipError_t launch_brick_occupancy(const uint8_t *bits, Dims d, uint8_t *occ, hipStream_t s);
-hipError_t launch_smooth(const SmoothArgs &a, int radius, bool compose, int ty, hipStream_t s);
-hipError_t launch_delta_finalize(const float *partials, int nblocks, const int64_t *count,
-                                 double *out, float inv_dummy, hipStream_t s);
 hipError_t launch_restrict_pass(const float *in, float *out, Dims din, int axis, const float *w,
                                 int radius, hipStream_t s);
 hipError_t launch_prolong(const float *const uc[3], Dims dc, float *const uf[3], Dims df,
@@ -79,7 +108,6 @@ hipError_t launch_sign_stats(const float *T0, const uint8_t *tbits, const uint8_
 hipError_t launch_dilate_bit(const uint8_t *bits, int bit, Dims d, const int margin[3],
                              uint8_t *rowdist, uint8_t *out, hipStream_t s);
 
-int force_partial_blocks(Dims d, int ty, int tz);
 
 // brick grid of the mask occupancy map (8x8x8 voxels per brick)
 inline Dims brick_dims(Dims d) { return Dims{(d.nx + 7) / 8, (d.ny + 7) / 8, (d.nz + 7) / 8}; }

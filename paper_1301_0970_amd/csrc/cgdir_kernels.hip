@@ -113,11 +113,11 @@ struct TileCoord {
     int x0, y0, z0, z1;
 };
 
-__device__ __forceinline__ TileCoord tile_of(int ty_rows, int tz, const Dims &d)
+// logical tile L of a volume: z chunk fastest, then x tile, then y tile
+__device__ __forceinline__ TileCoord tile_of(int ty_rows, int tz, const Dims &d, int L)
 {
-    const int ntx = (d.nx + kTileX - 1) / kTileX, nty = (d.ny + ty_rows - 1) / ty_rows;
+    const int ntx = (d.nx + kTileX - 1) / kTileX;
     const int nzc = (d.nz + tz - 1) / tz;
-    const int L = xcd_logical(blockIdx.x, ntx * nty * nzc);
     const int zc = L % nzc, t = L / nzc;
     TileCoord c;
     c.x0 = (t % ntx) * kTileX;
@@ -162,7 +162,7 @@ __device__ __forceinline__ float warp_masked(const ForceArgs &a, int px, int py,
 // points directly from global memory.
 // ============================================================================
 template <int TY>
-__global__ void __launch_bounds__(kTileX *TY) k_force(ForceArgs a)
+__device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
 {
     constexpr int TXH = kTileX + 2, CELLS = TXH * (TY + 2), NT = kTileX * TY;
     constexpr int NP = (CELLS + NT - 1) / NT;  // cells per thread and plane
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kTileX *TY) k_force(ForceArgs a)
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
-    const TileCoord tc = tile_of(TY, a.tz, a.d);
+    const TileCoord tc = tile_of(TY, a.tz, a.d, L);
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
     const bool masked = a.mbits != nullptr;
 
@@ -421,9 +421,37 @@ __global__ void __launch_bounds__(kTileX *TY) k_force(ForceArgs a)
             float s = 0.f;
 #pragma unroll
             for (int w = 0; w < NT / 64; ++w) s += red[w];
-            a.partials[blockIdx.x] = s;
+            a.partials[L] = s;
         }
     }
+}
+
+// number of tiles (blocks) of a volume for a tile of 64 x TY columns and TZ planes
+__device__ __host__ __forceinline__ int tile_count(const Dims &d, int ty_rows, int tz)
+{
+    return ((d.nx + kTileX - 1) / kTileX) * ((d.ny + ty_rows - 1) / ty_rows) * ((d.nz + tz - 1) / tz);
+}
+
+// pair owning logical block L of a batched launch: prefix[q] <= L < prefix[q + 1]
+__device__ __forceinline__ int pair_of(const int *prefix, int n, int L)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= L) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// one launch over the tiles of several pairs (each pair at its own level and size); the
+// pair descriptors travel in the kernel-argument segment and are read with scalar loads
+template <int TY>
+__global__ void __launch_bounds__(kTileX *TY) k_force_batch(ForceBatch b)
+{
+    const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
+    const int q = pair_of(b.prefix, b.n, L);
+    force_tile<TY>(b.d[q], L - b.prefix[q]);
 }
 
 // Moving-mask occupancy of 8x8x8 bricks: OR of the mask bits over the brick grown by one
@@ -451,7 +479,7 @@ __global__ void __launch_bounds__(256) k_brick_occupancy(const uint8_t *__restri
 // out(x) = s(x) + u(x + s(x)) per component (u gathered trilinearly).
 // ============================================================================
 template <int R, int TY, bool COMPOSE>
-__global__ void __launch_bounds__(kTileX *TY) k_smooth(SmoothArgs a)
+__device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
 {
     constexpr int WD = kTileX + 2 * R, HT = TY + 2 * R, NT = kTileX * TY;
     constexpr int CELLS = HT * WD, NP = (CELLS + NT - 1) / NT;
@@ -464,7 +492,7 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth(SmoothArgs a)
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
-    const TileCoord tc = tile_of(TY, a.tz, a.d);
+    const TileCoord tc = tile_of(TY, a.tz, a.d, L);
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
     float w[R + 1];
 #pragma unroll
@@ -652,16 +680,24 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth(SmoothArgs a)
     }
 }
 
+template <int R, int TY, bool COMPOSE>
+__global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
+{
+    const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
+    const int q = pair_of(b.prefix, b.n, L);
+    smooth_tile<R, TY, COMPOSE>(b.d[q], L - b.prefix[q]);
+}
+
 // ============================================================================
 // Stopping metric: delta = sqrt(sum of the per-block partials / |UROI|), summed in a fixed
 // order in double precision (kernel 5).
 // ============================================================================
-__global__ void __launch_bounds__(256) k_delta_finalize(const float *partials, int nblocks,
-                                                        const int64_t *count, double *out)
+__global__ void __launch_bounds__(256) k_delta_finalize_batch(DeltaBatch b)
 {
+    const DeltaJob &j = b.d[blockIdx.x];
     __shared__ double red[256];
     double s = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += 256) s += (double)partials[i];
+    for (int i = threadIdx.x; i < j.nblocks; i += 256) s += (double)j.partials[i];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -669,8 +705,8 @@ __global__ void __launch_bounds__(256) k_delta_finalize(const float *partials, i
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const int64_t n = *count;
-        out[0] = n > 0 ? sqrt(red[0] / (double)n) : 0.0;
+        const int64_t n = *j.count;
+        j.out[0] = n > 0 ? sqrt(red[0] / (double)n) : 0.0;
     }
 }
 
@@ -930,73 +966,73 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 static int tiles_xy(Dims d, int ty) { return ((d.nx + kTileX - 1) / kTileX) * ((d.ny + ty - 1) / ty); }
 
-int force_partial_blocks(Dims d, int ty, int tz) { return tiles_xy(d, ty) * ((d.nz + tz - 1) / tz); }
+int tile_blocks(Dims d, int ty, int tz) { return tiles_xy(d, ty) * ((d.nz + tz - 1) / tz); }
 
 template <int TY>
-static hipError_t force_ty(const ForceArgs &a, hipStream_t s)
+static hipError_t force_batch_ty(const ForceBatch &b, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_force<TY>), dim3(force_partial_blocks(a.d, TY, a.tz)), dim3(kTileX * TY), 0, s, a);
+    hipLaunchKernelGGL((k_force_batch<TY>), dim3(b.prefix[b.n]), dim3(kTileX * TY), 0, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_force(const ForceArgs &a, int ty, hipStream_t s, int *blocks_out)
+hipError_t launch_force_batch(const ForceBatch &b, int ty, hipStream_t s)
 {
-    if (blocks_out) *blocks_out = force_partial_blocks(a.d, ty, a.tz);
+    if (b.n < 1 || b.n > kBatchForce || b.prefix[b.n] < 1) return hipErrorInvalidValue;
     switch (ty) {
-    case 4: return force_ty<4>(a, s);
-    case 8: return force_ty<8>(a, s);
-    case 16: return force_ty<16>(a, s);
+    case 4: return force_batch_ty<4>(b, s);
+    case 8: return force_batch_ty<8>(b, s);
+    case 16: return force_batch_ty<16>(b, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int R, int TY>
+static hipError_t smooth_batch_r_ty(const SmoothBatch &b, bool compose, hipStream_t s)
+{
+    if (compose)
+        hipLaunchKernelGGL((k_smooth_batch<R, TY, true>), dim3(b.prefix[b.n]), dim3(kTileX * TY), 0, s, b);
+    else
+        hipLaunchKernelGGL((k_smooth_batch<R, TY, false>), dim3(b.prefix[b.n]), dim3(kTileX * TY), 0, s, b);
+    return hipGetLastError();
+}
+
+template <int TY>
+static hipError_t smooth_batch_ty(const SmoothBatch &b, int radius, bool compose, hipStream_t s)
+{
+    switch (radius) {
+    case 0: return smooth_batch_r_ty<0, TY>(b, compose, s);
+    case 1: return smooth_batch_r_ty<1, TY>(b, compose, s);
+    case 2: return smooth_batch_r_ty<2, TY>(b, compose, s);
+    case 3: return smooth_batch_r_ty<3, TY>(b, compose, s);
+    case 4: return smooth_batch_r_ty<4, TY>(b, compose, s);
+    case 5: return smooth_batch_r_ty<5, TY>(b, compose, s);
+    case 6: return smooth_batch_r_ty<6, TY>(b, compose, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, bool compose, int ty, hipStream_t s)
+{
+    if (b.n < 1 || b.n > kBatchSmooth || b.prefix[b.n] < 1) return hipErrorInvalidValue;
+    switch (ty) {
+    case 4: return smooth_batch_ty<4>(b, radius, compose, s);
+    case 8: return smooth_batch_ty<8>(b, radius, compose, s);
+    case 16: return smooth_batch_ty<16>(b, radius, compose, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_delta_batch(const DeltaBatch &b, hipStream_t s)
+{
+    if (b.n < 1 || b.n > kBatchDelta) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_delta_finalize_batch, dim3(b.n), dim3(256), 0, s, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_brick_occupancy(const uint8_t *bits, Dims d, uint8_t *occ, hipStream_t s)
 {
     const Dims db = brick_dims(d);
     hipLaunchKernelGGL(k_brick_occupancy, dim3(blocks_for(db.n(), 256)), dim3(256), 0, s, bits, d, db, occ);
-    return hipGetLastError();
-}
-
-template <int R, int TY>
-static hipError_t smooth_r_ty(const SmoothArgs &a, bool compose, hipStream_t s)
-{
-    dim3 grid(tiles_xy(a.d, TY) * ((a.d.nz + a.tz - 1) / a.tz));
-    if (compose)
-        hipLaunchKernelGGL((k_smooth<R, TY, true>), grid, dim3(kTileX * TY), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_smooth<R, TY, false>), grid, dim3(kTileX * TY), 0, s, a);
-    return hipGetLastError();
-}
-
-template <int TY>
-static hipError_t smooth_ty(const SmoothArgs &a, int radius, bool compose, hipStream_t s)
-{
-    switch (radius) {
-    case 0: return smooth_r_ty<0, TY>(a, compose, s);
-    case 1: return smooth_r_ty<1, TY>(a, compose, s);
-    case 2: return smooth_r_ty<2, TY>(a, compose, s);
-    case 3: return smooth_r_ty<3, TY>(a, compose, s);
-    case 4: return smooth_r_ty<4, TY>(a, compose, s);
-    case 5: return smooth_r_ty<5, TY>(a, compose, s);
-    case 6: return smooth_r_ty<6, TY>(a, compose, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_smooth(const SmoothArgs &a, int radius, bool compose, int ty, hipStream_t s)
-{
-    switch (ty) {
-    case 4: return smooth_ty<4>(a, radius, compose, s);
-    case 8: return smooth_ty<8>(a, radius, compose, s);
-    case 16: return smooth_ty<16>(a, radius, compose, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_delta_finalize(const float *partials, int nblocks, const int64_t *count, double *out,
-                                 float, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_delta_finalize, dim3(1), dim3(256), 0, s, partials, nblocks, count, out);
     return hipGetLastError();
 }
 

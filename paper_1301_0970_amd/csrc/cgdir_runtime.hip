@@ -169,7 +169,7 @@ size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, 
     if (k > 0) b += 2 * align_up(n0) + align_up((size_t)brick_dims(d0).n());  // bit-planes, occupancy
     if (want_delta(p)) {
         b += align_up(n0);  // UROI
-        b += align_up((size_t)force_partial_blocks(d0, t.force_ty, t.force_tz) * sizeof(float));
+        b += align_up((size_t)tile_blocks(d0, t.force_ty, t.force_tz) * sizeof(float));
         b += align_up((size_t)std::max(p.iters[0], 1) * sizeof(double));
     }
     b += align_up(8192);  // counters, flags, reduction partials
@@ -473,7 +473,7 @@ struct Job {
         }
         if (delta_on) {
             uroi = (uint8_t *)take(n0);
-            partials = (float *)take((size_t)force_partial_blocks(d0, ctx->tune.force_ty, ctx->tune.force_tz) *
+            partials = (float *)take((size_t)tile_blocks(d0, ctx->tune.force_ty, ctx->tune.force_tz) *
                                      sizeof(float));
             delta_dev = (double *)take((size_t)std::max(req.params.iters[0], 1) * sizeof(double));
             ok = ok && uroi && partials && delta_dev;
@@ -598,13 +598,13 @@ struct Job {
         return CGDIR_OK;
     }
 
-    // one iteration of the loop at the current level
-    int iterate()
+    // ---- one iteration of the loop at the current level, as batched-launch descriptors
+    bool metric() const { return delta_on && level == 0; }
+
+    ForceArgs force_args() const
     {
-        hipStream_t s = ctx->stream;
         const Dims d = level_dims(d0, level);
         const bool contour = contour_at(level);
-        const bool metric = delta_on && level == 0;
         ForceArgs fa{};
         fa.I0 = I0[level];
         fa.T0 = T0[level];
@@ -614,8 +614,8 @@ struct Job {
         const Dims db = brick_dims(d);
         fa.bnx = db.nx;
         fa.bny = db.ny;
-        fa.uroi = metric ? uroi : nullptr;
-        fa.partials = metric ? partials : nullptr;
+        fa.uroi = metric() ? uroi : nullptr;
+        fa.partials = metric() ? partials : nullptr;
         for (int c = 0; c < 3; ++c) {
             fa.u[c] = comp(ubuf, c);
             fa.du[c] = comp(dubuf, c);
@@ -631,35 +631,47 @@ struct Job {
         fa.c0 = req.params.intensity_offset;
         fa.inv_norm = 1.0f / req.params.norm_range;
         fa.tz = ctx->tune.force_tz;
-        int nblocks = 0;
-        HIP_TRY(timed(ctx, K_FORCE * 8 + level, (double)d.n(), [&] { return launch_force(fa, ctx->tune.force_ty, s, &nblocks); }));
-        if (metric)
-            HIP_TRY(timed(ctx, K_DELTA * 8 + level, 0.0, [&] {
-                return launch_delta_finalize(partials, nblocks, misc_i64, delta_dev + iter, 0.f, s);
-            }));
+        return fa;
+    }
+
+    DeltaJob delta_job() const
+    {
+        DeltaJob j;
+        j.partials = partials;
+        j.nblocks = tile_blocks(level_dims(d0, level), ctx->tune.force_ty, ctx->tune.force_tz);
+        j.count = misc_i64;
+        j.out = delta_dev + iter;
+        return j;
+    }
+
+    // smooth du, compose with u -> u_c
+    SmoothArgs compose_args() const
+    {
         SmoothArgs sa{};
         for (int c = 0; c < 3; ++c) {
             sa.in[c] = comp(dubuf, c);
             sa.u[c] = comp(ubuf, c);
             sa.out[c] = comp(ucbuf, c);
         }
-        sa.d = d;
+        sa.d = level_dims(d0, level);
         sa.tz = ctx->tune.smooth_tz;
         for (int m = 0; m <= kMaxRadius; ++m) sa.w[m] = wf[m];
-        HIP_TRY(timed(ctx, K_SMOOTH_COMPOSE * 8 + level, (double)d.n(),
-                      [&] { return launch_smooth(sa, Rf, true, ctx->tune.smooth_ty, s); }));
+        return sa;
+    }
+
+    // smooth u_c -> u
+    SmoothArgs smooth_args() const
+    {
         SmoothArgs sb{};
         for (int c = 0; c < 3; ++c) {
             sb.in[c] = comp(ucbuf, c);
             sb.u[c] = nullptr;
             sb.out[c] = comp(ubuf, c);
         }
-        sb.d = d;
+        sb.d = level_dims(d0, level);
         sb.tz = ctx->tune.smooth_tz;
         for (int m = 0; m <= kMaxRadius; ++m) sb.w[m] = wd[m];
-        HIP_TRY(timed(ctx, K_SMOOTH * 8 + level, (double)d.n(), [&] { return launch_smooth(sb, Rd, false, ctx->tune.smooth_ty, s); }));
-        ++iter;
-        return CGDIR_OK;
+        return sb;
     }
 
     int end_level()
@@ -678,37 +690,46 @@ struct Job {
                h[n - W] - h[n] <= (double)req.params.stop_eps;
     }
 
-    // advance by at most `budget` iterations; returns CGDIR_OK, sets `finished`
-    int advance(int budget, bool allow_sync)
+    // bring the job to a level with an iteration to run (prolongation, empty levels), or
+    // mark it finished
+    int prepare()
     {
-        while (budget > 0 && !finished) {
+        while (!finished) {
             if (!level_started) CG_TRY(begin_level());
-            const int total = req.params.iters[level];
-            bool stop = false;
-            if (iter < total) {
-                CG_TRY(iterate());
-                --budget;
-                if (req.params.stop_mode && level == 0 && iter % req.params.stop_window == 0 && allow_sync) {
-                    delta_host.resize(iter);
-                    HIP_TRY(hipMemcpyAsync(delta_host.data(), delta_dev, iter * sizeof(double), hipMemcpyDeviceToHost,
-                                           ctx->stream));
-                    HIP_TRY(hipStreamSynchronize(ctx->stream));
-                    stop = stop_due(delta_host);
-                }
-            }
-            if (iter >= total || stop) {
-                CG_TRY(end_level());
-                if (level == 0) {
-                    iters_done0 = iter;
-                    finished = true;
-                } else {
-                    --level;
-                    iter = 0;
-                    level_started = false;
-                }
+            if (iter < req.params.iters[level]) return CGDIR_OK;
+            CG_TRY(end_level());
+            if (level == 0) {
+                iters_done0 = iter;
+                finished = true;
+            } else {
+                --level;
+                iter = 0;
+                level_started = false;
             }
         }
         return CGDIR_OK;
+    }
+
+    // bookkeeping after the iteration's launches: stopping rule (reads delta back every
+    // stop_window iterations), end of level
+    int after_iteration()
+    {
+        ++iter;
+        bool stop = false;
+        if (req.params.stop_mode && level == 0 && iter % req.params.stop_window == 0) {
+            delta_host.resize(iter);
+            HIP_TRY(hipMemcpyAsync(delta_host.data(), delta_dev, iter * sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+            stop = stop_due(delta_host);
+        }
+        if (stop) {
+            CG_TRY(end_level());
+            iters_done0 = iter;
+            finished = true;
+            return CGDIR_OK;
+        }
+        return prepare();
     }
 
     // copy the result out (asynchronous on the stream)
@@ -732,6 +753,78 @@ struct Job {
         return bad ? CGDIR_E_NONFINITE : CGDIR_OK;
     }
 };
+
+// ------------------------------------------------------------------ one tick
+// One iteration of every job that has work left, as batched launches: each phase (force,
+// metric, smooth+compose, smooth) is one launch over the tiles of up to kBatchForce /
+// kBatchSmooth jobs (the smoothing launches are grouped by Gaussian radius).  A job that
+// fails stops with its code in `codes`; the others go on.
+namespace cgdir {
+namespace {
+
+int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &codes)
+{
+    hipStream_t s = c->stream;
+    std::vector<int> act;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        if (codes[i] != CGDIR_OK || jobs[i]->finished) continue;
+        codes[i] = jobs[i]->prepare();
+        if (codes[i] == CGDIR_OK && !jobs[i]->finished) act.push_back((int)i);
+    }
+    if (act.empty()) return CGDIR_OK;
+    int lvl = jobs[act[0]]->level;  // profiling slot: the common level, 6 when mixed
+    for (int i : act)
+        if (jobs[i]->level != lvl) lvl = 6;
+    const Tuning &t = c->tune;
+
+    for (size_t b = 0; b < act.size(); b += kBatchForce) {
+        ForceBatch fb{};
+        fb.n = (int)std::min<size_t>(kBatchForce, act.size() - b);
+        double vox = 0.0;
+        for (int q = 0; q < fb.n; ++q) {
+            fb.d[q] = jobs[act[b + q]]->force_args();
+            fb.prefix[q + 1] = fb.prefix[q] + tile_blocks(fb.d[q].d, t.force_ty, t.force_tz);
+            vox += (double)fb.d[q].d.n();
+        }
+        HIP_TRY(timed(c, K_FORCE * 8 + lvl, vox, [&] { return launch_force_batch(fb, t.force_ty, s); }));
+    }
+    {
+        DeltaBatch db{};
+        for (size_t i = 0; i <= act.size(); ++i) {
+            if (i < act.size() && jobs[act[i]]->metric()) db.d[db.n++] = jobs[act[i]]->delta_job();
+            if (db.n > 0 && (db.n == kBatchDelta || i == act.size())) {
+                HIP_TRY(timed(c, K_DELTA * 8 + lvl, 0.0, [&] { return launch_delta_batch(db, s); }));
+                db.n = 0;
+            }
+        }
+    }
+    for (int phase = 0; phase < 2; ++phase) {
+        const bool compose = phase == 0;
+        std::map<int, std::vector<int>> by_radius;
+        for (int i : act) by_radius[compose ? jobs[i]->Rf : jobs[i]->Rd].push_back(i);
+        for (auto &g : by_radius) {
+            const std::vector<int> &v = g.second;
+            for (size_t b = 0; b < v.size(); b += kBatchSmooth) {
+                SmoothBatch sb{};
+                sb.n = (int)std::min<size_t>(kBatchSmooth, v.size() - b);
+                double vox = 0.0;
+                for (int q = 0; q < sb.n; ++q) {
+                    sb.d[q] = compose ? jobs[v[b + q]]->compose_args() : jobs[v[b + q]]->smooth_args();
+                    sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, t.smooth_ty, t.smooth_tz);
+                    vox += (double)sb.d[q].d.n();
+                }
+                const int id = compose ? K_SMOOTH_COMPOSE : K_SMOOTH;
+                HIP_TRY(timed(c, id * 8 + lvl, vox,
+                              [&] { return launch_smooth_batch(sb, g.first, compose, t.smooth_ty, s); }));
+            }
+        }
+    }
+    for (int i : act) codes[i] = jobs[i]->after_iteration();
+    return CGDIR_OK;
+}
+
+}  // namespace
+}  // namespace cgdir
 
 // ------------------------------------------------------------------ serving state
 
@@ -814,13 +907,23 @@ void scheduler(cgdir_ctx *c)
         // one tick: every admitted request advances one iteration
         {
             std::lock_guard<std::mutex> lg(c->launch_mu);
-            for (cgdir_ctx::Request *r : active) {
-                if (r->job.finished) continue;
-                int rc = r->job.advance(1, true);
-                if (rc != CGDIR_OK) {
-                    r->job.finished = true;
-                    r->error = rc;
+            std::vector<Job *> tj;
+            std::vector<cgdir_ctx::Request *> tr;
+            for (cgdir_ctx::Request *r : active)
+                if (!r->job.finished && r->error == CGDIR_OK) {
+                    tj.push_back(&r->job);
+                    tr.push_back(r);
                 }
+            std::vector<int> codes(tj.size(), CGDIR_OK);
+            const int rc = tj.empty() ? CGDIR_OK : run_tick(c, tj, codes);
+            for (size_t i = 0; i < tj.size(); ++i) {
+                const int code = rc != CGDIR_OK ? rc : codes[i];
+                if (code != CGDIR_OK) {
+                    tr[i]->job.finished = true;
+                    tr[i]->error = code;
+                }
+            }
+            for (cgdir_ctx::Request *r : active) {
                 if (r->job.finished && !r->emitted) {
                     if (r->error == CGDIR_OK) r->error = r->job.emit();
                     r->done_ev = get_ev();
@@ -1012,7 +1115,13 @@ int cgdir_register(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume 
     {
         std::lock_guard<std::mutex> lg(c->launch_mu);
         rc = job.setup();
-        if (rc == CGDIR_OK) rc = job.advance(1 << 30, true);
+        std::vector<Job *> jobs{&job};
+        std::vector<int> codes{rc};
+        while (codes[0] == CGDIR_OK && !job.finished) {
+            const int t = run_tick(c, jobs, codes);
+            if (t != CGDIR_OK) codes[0] = t;
+        }
+        rc = codes[0];
         if (rc == CGDIR_OK) rc = job.emit();
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess && rc == CGDIR_OK) rc = CGDIR_E_HIP;
@@ -1045,16 +1154,19 @@ int cgdir_register_batch(cgdir_ctx *c, int n, const cgdir_request *reqs, int *st
         std::lock_guard<std::mutex> lg(c->launch_mu);
         for (int i = 0; i < n; ++i)
             if (st[i] == CGDIR_OK) st[i] = jobs[i]->setup();
-        bool more = true;
-        while (more) {  // one iteration of every unfinished pair per round
-            more = false;
-            for (int i = 0; i < n; ++i) {
-                if (st[i] != CGDIR_OK || jobs[i]->finished) continue;
-                st[i] = jobs[i]->advance(1, true);
-                if (st[i] == CGDIR_OK && jobs[i]->finished) st[i] = jobs[i]->emit();
-                more = more || (st[i] == CGDIR_OK && !jobs[i]->finished);
-            }
+        std::vector<Job *> jp;
+        for (auto &j : jobs) jp.push_back(j.get());
+        for (;;) {  // one iteration of every unfinished pair per tick
+            bool more = false;
+            for (int i = 0; i < n; ++i) more = more || (st[i] == CGDIR_OK && !jobs[i]->finished);
+            if (!more) break;
+            const int t = run_tick(c, jp, st);
+            if (t != CGDIR_OK)
+                for (int i = 0; i < n; ++i)
+                    if (st[i] == CGDIR_OK && !jobs[i]->finished) st[i] = t;
         }
+        for (int i = 0; i < n; ++i)
+            if (st[i] == CGDIR_OK) st[i] = jobs[i]->emit();
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess) first = CGDIR_E_HIP;
     for (int i = 0; i < n; ++i) {

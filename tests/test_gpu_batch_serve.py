@@ -129,3 +129,29 @@ def test_cancel_and_oversize():
         with pytest.raises(cgdir.CgdirError) as e:
             ctx.submit(big, big, None, None, cgdir.make_params(), torch.empty((3, 128, 512, 512), device="cuda"))
         assert e.value.code == cgdir.E_NOMEM
+
+
+def test_batch_of_many_small_pairs_spans_several_launches():
+    """More pairs than one launch's descriptor table holds (16 for the force, 24 for the
+    smoothing): chunked launches, results still equal to each pair alone."""
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pairs = []
+    for i in range(26):
+        dims = (40 + 8 * (i % 5), 36 + 4 * (i % 3), 16 + 2 * (i % 4))
+        if i % 3 == 0:
+            pairs.append(P.plain_pair(dims=dims, amp=1.5, iters=3, seed=100 + i))
+        else:
+            pairs.append(P.head_neck_pair(dims=dims, amp=1.5, k=1 + i % 4, levels=2, iters=2,
+                                          sigma=1.5 if i % 2 else 1.0, seed=100 + i))
+    items = _items(pairs)
+    prms = [cgdir.params_for_pair(p) for p in pairs]
+    with cgdir.Context(2 << 30) as ctx:
+        say("alone x26")
+        alone = [ctx.register(*it, prm=pr).cpu().numpy() for it, pr in zip(items, prms)]
+        outs = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
+        say("batch x26")
+        rc, st = ctx.register_batch(items, prms, outs)
+        assert rc == cgdir.OK and st == [0] * len(pairs)
+        for a, o in zip(alone, outs):
+            np.testing.assert_array_equal(a, o.cpu().numpy())

@@ -29,7 +29,8 @@ struct ForceArgs {
     const uint8_t *uroi;      // stopping region (or null: no metric)
     const float *u[3];        // current field
     float *du[3];             // output step
-    float *partials;          // per-block sums of ((T0 - I0~)/norm)^2 over the UROI
+    float *partials;          // sums of ((T0 - I0~)/norm)^2 over the UROI, one per 64-voxel
+                              // row segment: index (z * ny + y) * ceil(nx / 64) + x / 64
     Dims d;
     int bnx, bny;             // brick grid x, y extents
     int k;                    // active structures (<= kMaxStructs)
@@ -54,7 +55,7 @@ struct SmoothArgs {
 // One pair's stopping-metric reduction in a batched finalize.
 struct DeltaJob {
     const float *partials;
-    int nblocks;
+    int nparts;
     const int64_t *count;
     double *out;
 };
@@ -108,6 +109,9 @@ hipError_t launch_sign_stats(const float *T0, const uint8_t *tbits, const uint8_
 hipError_t launch_dilate_bit(const uint8_t *bits, int bit, Dims d, const int margin[3],
                              uint8_t *rowdist, uint8_t *out, hipStream_t s);
 
+
+// row-segment partials of the stopping metric for a volume
+inline int64_t metric_parts(Dims d) { return (int64_t)((d.nx + kTileX - 1) / kTileX) * d.ny * d.nz; }
 
 // brick grid of the mask occupancy map (8x8x8 voxels per brick)
 inline Dims brick_dims(Dims d) { return Dims{(d.nx + 7) / 8, (d.ny + 7) / 8, (d.nz + 7) / 8}; }

@@ -169,7 +169,6 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
     __shared__ float W[4][CELLS];               // ring of warped planes, slot (p - z0 + 1) & 3
     __shared__ float K[4][CELLS];               // K_i~ of the cell's structure when exactly one
     __shared__ uint8_t F[4][CELLS];             // structures touching the cell's stencil
-    __shared__ float red[NT / 64];
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
@@ -302,8 +301,8 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
     load_target(z0);
     __syncthreads();
 
-    float dacc = 0.f;
     for (int z = z0; z < z1; ++z) {
+        float dsq = 0.f;
         // (1) gathers of plane z + 2 and the u of plane z + 3 go in flight
         const bool ahead = z + 2 <= z1;
         if (ahead) {
@@ -404,8 +403,14 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
             a.du[2][v] = dz;
             if (in_uroi) {
                 const float e = d * a.inv_norm;
-                dacc = __builtin_fmaf(e, e, dacc);
+                dsq = e * e;
             }
+        }
+        // stopping metric: one partial per 64-voxel row segment (a wave is one tile row),
+        // a grouping that does not depend on the launch geometry
+        if (a.partials != nullptr && gy < ny) {
+            const float r = wave_sum(dsq);
+            if (tx == 0) a.partials[(z * ny + gy) * ((nx + kTileX - 1) / kTileX) + x0 / kTileX] = r;
         }
         // (3) the target row of plane z + 1, then the warped plane z + 2 into the ring
         load_target(z + 1);
@@ -413,17 +418,6 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
         __syncthreads();
     }
 
-    if (a.partials != nullptr) {  // uniform over the launch
-        dacc = wave_sum(dacc);
-        if ((tid & 63) == 0) red[tid >> 6] = dacc;
-        __syncthreads();
-        if (tid == 0) {
-            float s = 0.f;
-#pragma unroll
-            for (int w = 0; w < NT / 64; ++w) s += red[w];
-            a.partials[L] = s;
-        }
-    }
 }
 
 // number of tiles (blocks) of a volume for a tile of 64 x TY columns and TZ planes
@@ -697,7 +691,7 @@ __global__ void __launch_bounds__(256) k_delta_finalize_batch(DeltaBatch b)
     const DeltaJob &j = b.d[blockIdx.x];
     __shared__ double red[256];
     double s = 0.0;
-    for (int i = threadIdx.x; i < j.nblocks; i += 256) s += (double)j.partials[i];
+    for (int i = threadIdx.x; i < j.nparts; i += 256) s += (double)j.partials[i];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <string>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -169,7 +170,7 @@ size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, 
     if (k > 0) b += 2 * align_up(n0) + align_up((size_t)brick_dims(d0).n());  // bit-planes, occupancy
     if (want_delta(p)) {
         b += align_up(n0);  // UROI
-        b += align_up((size_t)tile_blocks(d0, t.force_ty, t.force_tz) * sizeof(float));
+        b += align_up((size_t)metric_parts(d0) * sizeof(float));
         b += align_up((size_t)std::max(p.iters[0], 1) * sizeof(double));
     }
     b += align_up(8192);  // counters, flags, reduction partials
@@ -182,6 +183,110 @@ enum KernelId { K_FORCE, K_SMOOTH_COMPOSE, K_SMOOTH, K_DELTA, K_RESTRICT, K_PROL
                 K_WARP, K_MISC, K_COUNT };
 const char *kKernelNames[K_COUNT] = {"force", "smooth_compose", "smooth", "delta", "restrict",
                                      "prolong", "pack_masks", "uroi", "warp", "misc"};
+
+// ------------------------------------------------------------------ tile autotuner
+// A pair's results do not depend on the tile shape of any kernel, so the first launches of
+// each (kernel, shapes) group rotate through candidate shapes, each timed with HIP events
+// on the stream; once every candidate has been timed, the fastest is kept for the group for
+// the rest of the context's life.  CGDIR_TUNE fixes the shapes instead.
+struct TileCfg {
+    int ty, tz;
+};
+const TileCfg kForceCands[] = {{4, 8}, {4, 4}, {4, 16}, {8, 8}, {8, 16}, {16, 8}};
+const TileCfg kSmoothCands[] = {{8, 32}, {8, 16}, {16, 32}, {16, 16}, {4, 16}, {8, 8}, {4, 32}};
+
+class Tuner {
+  public:
+    bool enabled = true;
+    TileCfg fixed_force{4, 8}, fixed_smooth{8, 32};
+    bool log = false;
+
+    // shape to use for the next launch of group `key`; *measure >= 0 asks the caller to time
+    // the launch with events ev[0], ev[1] and hand them back through record()
+    TileCfg choose(bool force, const std::string &key, int *measure)
+    {
+        *measure = -1;
+        const TileCfg *c = force ? kForceCands : kSmoothCands;
+        const int nc = force ? (int)(sizeof(kForceCands) / sizeof(TileCfg)) : (int)(sizeof(kSmoothCands) / sizeof(TileCfg));
+        if (!enabled) return force ? fixed_force : fixed_smooth;
+        Entry &e = table_[key];
+        if (e.ms.empty()) e.ms.assign(nc, -1.f);
+        if (e.best >= 0) return c[e.best];
+        poll(e);
+        bool all = true;
+        for (float m : e.ms) all = all && m >= 0.f;
+        if (all) {
+            e.best = 0;
+            for (int i = 1; i < nc; ++i)
+                if (e.ms[i] < e.ms[e.best]) e.best = i;
+            if (log) std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.4f ms)\n", key.c_str(), c[e.best].ty,
+                                  c[e.best].tz, e.ms[e.best]);
+            return c[e.best];
+        }
+        if (e.next < nc) {
+            *measure = e.next;
+            return c[e.next++];
+        }
+        return c[0];
+    }
+    void record(bool force, const std::string &key, int cand, hipEvent_t a, hipEvent_t b)
+    {
+        (void)force;
+        table_[key].pending.push_back({cand, a, b});
+    }
+    hipEvent_t event()
+    {
+        if (!spare_.empty()) {
+            hipEvent_t e = spare_.back();
+            spare_.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void release_all()
+    {
+        for (auto &kv : table_)
+            for (auto &p : kv.second.pending) {
+                hipEventSynchronize(p.b);
+                spare_.push_back(p.a);
+                spare_.push_back(p.b);
+            }
+        table_.clear();
+        for (hipEvent_t e : spare_) hipEventDestroy(e);
+        spare_.clear();
+    }
+
+  private:
+    struct Pending {
+        int cand;
+        hipEvent_t a, b;
+    };
+    struct Entry {
+        int next = 0, best = -1;
+        std::vector<float> ms;
+        std::vector<Pending> pending;
+    };
+    void poll(Entry &e)
+    {
+        for (size_t i = 0; i < e.pending.size();) {
+            Pending &p = e.pending[i];
+            if (hipEventQuery(p.b) == hipSuccess) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) e.ms[p.cand] = ms;
+                else e.ms[p.cand] = 1e30f;
+                spare_.push_back(p.a);
+                spare_.push_back(p.b);
+                e.pending.erase(e.pending.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+    }
+    std::map<std::string, Entry> table_;
+    std::vector<hipEvent_t> spare_;
+};
 
 }  // namespace
 }  // namespace cgdir
@@ -199,6 +304,7 @@ struct cgdir_ctx {
     int max_slots = 1;
     bool profile = false;
     Tuning tune;
+    Tuner tuner;
 
     // profiling
     std::mutex prof_mu;
@@ -473,8 +579,7 @@ struct Job {
         }
         if (delta_on) {
             uroi = (uint8_t *)take(n0);
-            partials = (float *)take((size_t)tile_blocks(d0, ctx->tune.force_ty, ctx->tune.force_tz) *
-                                     sizeof(float));
+            partials = (float *)take((size_t)metric_parts(d0) * sizeof(float));
             delta_dev = (double *)take((size_t)std::max(req.params.iters[0], 1) * sizeof(double));
             ok = ok && uroi && partials && delta_dev;
         }
@@ -638,7 +743,7 @@ struct Job {
     {
         DeltaJob j;
         j.partials = partials;
-        j.nblocks = tile_blocks(level_dims(d0, level), ctx->tune.force_ty, ctx->tune.force_tz);
+        j.nparts = (int)metric_parts(level_dims(d0, level));
         j.count = misc_i64;
         j.out = delta_dev + iter;
         return j;
@@ -777,16 +882,43 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
         if (jobs[i]->level != lvl) lvl = 6;
     const Tuning &t = c->tune;
 
+    auto shapes_key = [&](char kind, int radius, const int *idx, int n) {
+        std::string key(1, kind);
+        key += std::to_string(radius);
+        for (int q = 0; q < n; ++q) {
+            const Dims d = level_dims(jobs[idx[q]]->d0, jobs[idx[q]]->level);
+            key += ':' + std::to_string(d.nx) + 'x' + std::to_string(d.ny) + 'x' + std::to_string(d.nz);
+        }
+        return key;
+    };
+    // a launch, timed for the tuner when it asks
+    auto tuned = [&](bool measure_it, bool force, const std::string &key, int cand, auto &&fn) -> hipError_t {
+        if (!measure_it) return fn();
+        hipEvent_t ea = c->tuner.event(), eb = c->tuner.event();
+        if (!ea || !eb) return fn();
+        hipEventRecord(ea, s);
+        const hipError_t e = fn();
+        hipEventRecord(eb, s);
+        c->tuner.record(force, key, cand, ea, eb);
+        return e;
+    };
+
     for (size_t b = 0; b < act.size(); b += kBatchForce) {
         ForceBatch fb{};
         fb.n = (int)std::min<size_t>(kBatchForce, act.size() - b);
+        const std::string key = shapes_key('F', 0, &act[b], fb.n);
+        int cand = -1;
+        const TileCfg cfg = c->tuner.choose(true, key, &cand);
         double vox = 0.0;
         for (int q = 0; q < fb.n; ++q) {
             fb.d[q] = jobs[act[b + q]]->force_args();
-            fb.prefix[q + 1] = fb.prefix[q] + tile_blocks(fb.d[q].d, t.force_ty, t.force_tz);
+            fb.d[q].tz = cfg.tz;
+            fb.prefix[q + 1] = fb.prefix[q] + tile_blocks(fb.d[q].d, cfg.ty, cfg.tz);
             vox += (double)fb.d[q].d.n();
         }
-        HIP_TRY(timed(c, K_FORCE * 8 + lvl, vox, [&] { return launch_force_batch(fb, t.force_ty, s); }));
+        HIP_TRY(timed(c, K_FORCE * 8 + lvl, vox, [&] {
+            return tuned(cand >= 0, true, key, cand, [&] { return launch_force_batch(fb, cfg.ty, s); });
+        }));
     }
     {
         DeltaBatch db{};
@@ -807,15 +939,21 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
             for (size_t b = 0; b < v.size(); b += kBatchSmooth) {
                 SmoothBatch sb{};
                 sb.n = (int)std::min<size_t>(kBatchSmooth, v.size() - b);
+                const std::string key = shapes_key(compose ? 'C' : 'S', g.first, &v[b], sb.n);
+                int cand = -1;
+                const TileCfg cfg = c->tuner.choose(false, key, &cand);
                 double vox = 0.0;
                 for (int q = 0; q < sb.n; ++q) {
                     sb.d[q] = compose ? jobs[v[b + q]]->compose_args() : jobs[v[b + q]]->smooth_args();
-                    sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, t.smooth_ty, t.smooth_tz);
+                    sb.d[q].tz = cfg.tz;
+                    sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, cfg.ty, cfg.tz);
                     vox += (double)sb.d[q].d.n();
                 }
                 const int id = compose ? K_SMOOTH_COMPOSE : K_SMOOTH;
-                HIP_TRY(timed(c, id * 8 + lvl, vox,
-                              [&] { return launch_smooth_batch(sb, g.first, compose, t.smooth_ty, s); }));
+                HIP_TRY(timed(c, id * 8 + lvl, vox, [&] {
+                    return tuned(cand >= 0, false, key, cand,
+                                 [&] { return launch_smooth_batch(sb, g.first, compose, cfg.ty, s); });
+                }));
             }
         }
     }
@@ -1045,6 +1183,10 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
     c->max_slots = desc->max_slots;
     c->profile = (desc->flags & CGDIR_CTX_PROFILE) != 0;
     c->tune = tuning_from_env();
+    c->tuner.enabled = std::getenv("CGDIR_TUNE") == nullptr;
+    c->tuner.fixed_force = TileCfg{c->tune.force_ty, c->tune.force_tz};
+    c->tuner.fixed_smooth = TileCfg{c->tune.smooth_ty, c->tune.smooth_tz};
+    c->tuner.log = std::getenv("CGDIR_TUNE_LOG") != nullptr;
     if (desc->stream) {
         c->stream = (hipStream_t)desc->stream;
     } else {
@@ -1086,6 +1228,10 @@ int cgdir_destroy(cgdir_ctx *c)
         drain_profile(c);
         for (hipEvent_t e : c->spare_events) hipEventDestroy(e);
         c->spare_events.clear();
+    }
+    {
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        c->tuner.release_all();
     }
     if (c->own_pool) hipFree(c->own_pool);
     if (c->own_stream) hipStreamDestroy(c->stream);

@@ -18,21 +18,38 @@ struct Dims {
     __host__ __device__ int64_t n() const { return (int64_t)nx * ny * nz; }
 };
 
-// Arguments of the fused force kernel: warp of I0 (and of the masked images m_i (I0 + c0)),
-// central differences, Eq.7, optional stopping-metric partials.
-struct ForceArgs {
+// The warp of the moving image with the current field (kernel 4 on images):
+// I0~(x) = I0(x + u(x)); F(x) = OR of the moving-mask bits at the 8 corners of x's trilinear
+// stencil; where F has exactly one bit i, K(x) = (m_i (I0 + c0))(x + u(x)) (elsewhere K is
+// neither written nor read).
+struct WarpArgs {
     const float *I0;          // moving image at this level
-    const float *T0;          // target image at this level
-    const uint8_t *mbits;     // bit i = voxel inside structure i on the moving image (null: k = 0)
-    const uint8_t *tbits;     // same on the target image
+    const uint8_t *mbits;     // moving-mask bits (null: no contour terms at this level)
     const uint8_t *mocc;      // moving-mask occupancy of 8x8x8 bricks (brick_dims)
+    float *wI0;
+    uint8_t *F;
+    float *K;
+    Dims d;
+    int bnx, bny;             // brick grid x, y extents
+    float c0;                 // CT-number offset
+};
+
+// Arguments of the force kernel (gradient, Eq.7, stopping-metric partials) on the warped
+// image of the current field.
+struct ForceArgs {
+    const float *wI0;         // I0~ of the current field
+    const uint8_t *F;         // stencil structure bits (null: k = 0 at this level)
+    const float *K;           // K_i~ where F has one bit
+    const float *T0;          // target image at this level
+    const uint8_t *tbits;     // bit i = voxel inside structure i on the target image
     const uint8_t *uroi;      // stopping region (or null: no metric)
-    const float *u[3];        // current field
+    const float *I0;          // moving image, mask bits and field: re-warp where several
+    const uint8_t *mbits;     //   structures meet in one stencil
+    const float *u[3];
     float *du[3];             // output step
     float *partials;          // sums of ((T0 - I0~)/norm)^2 over the UROI, one per 64-voxel
                               // row segment: index (z * ny + y) * ceil(nx / 64) + x / 64
     Dims d;
-    int bnx, bny;             // brick grid x, y extents
     int k;                    // active structures (<= kMaxStructs)
     float lam[kMaxStructs];   // lambda_i
     float lam_sum;            // lambda_0 + ... + lambda_{k-1}, summed in this order
@@ -42,14 +59,16 @@ struct ForceArgs {
     int tz;                   // planes per block (z chunk)
 };
 
-// Arguments of the separable Gaussian kernels.
+// Arguments of the separable Gaussian kernels: smoothing of du followed by the composite
+// update (compose), or smoothing of u_c into u followed by the warp of I0 with that u.
 struct SmoothArgs {
     const float *in[3];
-    const float *u[3];        // compose mode: the field gathered at x + smoothed(in)
+    const float *u[3];        // compose: the field gathered at x + smoothed(in)
     float *out[3];
     Dims d;
     float w[kMaxRadius + 1];  // w[0] centre, w[m] = weight at +-m
     int tz;
+    WarpArgs warp;            // smoothing of u: where the warp goes
 };
 
 // One pair's stopping-metric reduction in a batched finalize.
@@ -63,7 +82,7 @@ struct DeltaJob {
 // Batched launches: one launch over the tiles of n pairs.  The descriptors travel in the
 // kernel-argument segment (<= 4 KiB), so a launch holds a bounded number of pairs.
 // prefix[q] = first block of pair q, prefix[n] = total blocks.
-constexpr int kBatchForce = 16, kBatchSmooth = 24, kBatchDelta = 64;
+constexpr int kBatchForce = 16, kBatchSmooth = 20, kBatchDelta = 64;
 struct ForceBatch {
     int n;
     int prefix[kBatchForce + 1];
@@ -85,6 +104,7 @@ static_assert(sizeof(ForceBatch) <= 4096 && sizeof(SmoothBatch) <= 4096 && sizeo
 hipError_t launch_force_batch(const ForceBatch &b, int ty, hipStream_t s);
 hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, bool compose, int ty, hipStream_t s);
 hipError_t launch_delta_batch(const DeltaBatch &b, hipStream_t s);
+hipError_t launch_warp_init(const WarpArgs &w, const float *const u[3], hipStream_t s);
 int tile_blocks(Dims d, int ty, int tz);
 hipError_t launch_brick_occupancy(const uint8_t *bits, Dims d, uint8_t *occ, hipStream_t s);
 hipError_t launch_restrict_pass(const float *in, float *out, Dims din, int axis, const float *w,

@@ -98,6 +98,13 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+struct Field3 {
+    const float *p[3];
+};
+struct Field3W {
+    float *p[3];
+};
+
 // XCD-aware block order.  The dispatcher hands consecutive block ids to the 8 XCDs in
 // turn; the blocks one XCD receives are mapped onto a contiguous range of logical tiles, so
 // that tiles sharing halo cache lines run on the same L2.  Logical order: z chunk fastest,
@@ -127,8 +134,8 @@ __device__ __forceinline__ TileCoord tile_of(int ty_rows, int tz, const Dims &d,
     return c;
 }
 
-// Warp of the masked moving image m_i (I0 + c0) at voxel (px, py, pz): K_i~ of the
-// decomposition below, for the structures selected by `bit`.
+// Warp of the masked moving image m_i (I0 + c0) at voxel (px, py, pz) with the field u:
+// K_i~ of the decomposition below, for the structures selected by `bit`.
 __device__ __forceinline__ float warp_masked(const ForceArgs &a, int px, int py, int pz, uint32_t bit)
 {
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
@@ -144,13 +151,78 @@ __device__ __forceinline__ float warp_masked(const ForceArgs &a, int px, int py,
 }
 
 // ============================================================================
-// Force: kernels 2 (gradient), 3 (moving vector, Eq.7) and the image half of kernel 4
-// (warp) fused.  A block owns a 64 x TY column tile and marches through a chunk of z
-// planes; the warped moving image I0~ = I0(x + u) of each plane (tile + 1-voxel halo)
-// goes to a 3-plane LDS ring from which the central differences are taken, together with
-// a flag telling whether any corner of the cell's trilinear stencil lies inside a moving
-// structure (looked up first in a coarse brick occupancy map, so that most cells never
-// touch the mask bits).
+// Warp of the moving image (kernel 4), split into issue (positions, gathers in flight)
+// and finish (interpolation, mask bits, stores) so that callers can overlap the gathers
+// with other work.  The moving-mask bits are read only where the brick occupancy map says
+// a structure is near.
+// ============================================================================
+struct WarpPending {
+    float g[8];
+    float t[3];
+    int b[3];
+    uint32_t occ;
+};
+
+__device__ __forceinline__ void warp_issue(const WarpArgs &w, int gx, int gy, int gz, float ux, float uy, float uz,
+                                           WarpPending &p)
+{
+    const int nx = w.d.nx, ny = w.d.ny, nz = w.d.nz, nxy = nx * ny;
+    const Split sx = split_axis(gx, ux, nx), sy = split_axis(gy, uy, ny), sz = split_axis(gz, uz, nz);
+    const Corners q = corners(sx, sy, sz, nx, nxy);
+    const float *__restrict__ I0 = w.I0;
+    p.g[0] = I0[q.r00 + q.x0];
+    p.g[1] = I0[q.r00 + q.x1];
+    p.g[2] = I0[q.r10 + q.x0];
+    p.g[3] = I0[q.r10 + q.x1];
+    p.g[4] = I0[q.r01 + q.x0];
+    p.g[5] = I0[q.r01 + q.x1];
+    p.g[6] = I0[q.r11 + q.x0];
+    p.g[7] = I0[q.r11 + q.x1];
+    p.t[0] = q.tx;
+    p.t[1] = q.ty;
+    p.t[2] = q.tz;
+    p.b[0] = sx.i0;
+    p.b[1] = sy.i0;
+    p.b[2] = sz.i0;
+    p.occ = w.mbits != nullptr ? w.mocc[(sx.i0 >> 3) + w.bnx * ((sy.i0 >> 3) + w.bny * (sz.i0 >> 3))] : 0u;
+}
+
+__device__ __forceinline__ void warp_finish(const WarpArgs &w, const WarpPending &p, int v)
+{
+    w.wI0[v] = lerp8(p.g, p.t[0], p.t[1], p.t[2]);
+    if (w.mbits == nullptr) return;
+    uint32_t any = 0;
+    if (p.occ) {  // a structure is near: mask bits at the 8 corners
+        const int nx = w.d.nx, ny = w.d.ny, nz = w.d.nz, nxy = nx * ny;
+        const int i0 = p.b[0], j0 = p.b[1], l0 = p.b[2];
+        const int i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
+        const uint8_t *__restrict__ mb = w.mbits;
+        uint32_t b[8];
+        b[0] = mb[i0 + nx * j0 + nxy * l0];
+        b[1] = mb[i1 + nx * j0 + nxy * l0];
+        b[2] = mb[i0 + nx * j1 + nxy * l0];
+        b[3] = mb[i1 + nx * j1 + nxy * l0];
+        b[4] = mb[i0 + nx * j0 + nxy * l1];
+        b[5] = mb[i1 + nx * j0 + nxy * l1];
+        b[6] = mb[i0 + nx * j1 + nxy * l1];
+        b[7] = mb[i1 + nx * j1 + nxy * l1];
+        any = b[0] | b[1] | b[2] | b[3] | b[4] | b[5] | b[6] | b[7];
+        if (any != 0 && (any & (any - 1)) == 0) {  // one structure: its K_i~ here
+            float h[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) h[m] = (b[m] & any) ? p.g[m] + w.c0 : 0.f;
+            w.K[v] = lerp8(h, p.t[0], p.t[1], p.t[2]);
+        }
+    }
+    w.F[v] = (uint8_t)any;
+}
+
+// ============================================================================
+// Force: kernels 2 (gradient) and 3 (moving vector, Eq.7) on the warped moving image.
+// A block owns a 64 x TY column tile and marches through a chunk of z planes; each plane
+// of I0~ and of the stencil structure bits (tile + 1-voxel halo) is prefetched into
+// registers one plane ahead and stored into a 4-slot LDS ring, from which the central
+// differences are taken (one barrier per plane).
 //
 // With s_i the sign of structure i (M_i = s_i m_i, N_i = s_i n_i), the modified images of
 // Eq.2 decompose exactly (trilinear interpolation and central differences are linear):
@@ -158,132 +230,53 @@ __device__ __forceinline__ float warp_masked(const ForceArgs &a, int px, int py,
 //   T_i - I_i~ = (T0 - I0~) + s_i/2 (n_i (T0 + c0) - K_i~),   K_i~ = (m_i (I0 + c0)) o (Id + u).
 // Where neither mask of structure i touches the stencil, K_i~ = n_i = 0 and its terms of
 // Eq.7 reduce to lambda_i a0 d (numerator) and lambda_i a0^2 (denominator): that is the
-// whole computation for most voxels.  Near a structure, K_i~ is evaluated at the 7 stencil
-// points directly from global memory.
+// whole computation for most voxels.  Where one structure touches it, K_i~ at the stencil
+// cells comes from the warp; where several do, K_i~ is re-evaluated from the field.
 // ============================================================================
 template <int TY>
 __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
 {
     constexpr int TXH = kTileX + 2, CELLS = TXH * (TY + 2), NT = kTileX * TY;
-    constexpr int NP = (CELLS + NT - 1) / NT;  // cells per thread and plane
-    __shared__ float W[4][CELLS];               // ring of warped planes, slot (p - z0 + 1) & 3
-    __shared__ float K[4][CELLS];               // K_i~ of the cell's structure when exactly one
-    __shared__ uint8_t F[4][CELLS];             // structures touching the cell's stencil
+    constexpr int NP = (CELLS + NT - 1) / NT;
+    __shared__ float W[4][CELLS];     // ring of I0~ planes, slot (p - z0 + 1) & 3
+    __shared__ uint8_t FB[4][CELLS];  // stencil structure bits
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
     const TileCoord tc = tile_of(TY, a.tz, a.d, L);
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
-    const bool masked = a.mbits != nullptr;
+    const bool masked = a.F != nullptr;
 
-    const float *__restrict__ I0 = a.I0;
-    const float *__restrict__ ux = a.u[0];
-    const float *__restrict__ uy = a.u[1];
-    const float *__restrict__ uz = a.u[2];
-
-    // the cells (tile + 1-voxel halo) this thread warps, as clamped volume coordinates
-    int cgx[NP], cgy[NP];
+    int coff[NP];
     bool cval[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int c = tid + j * NT;
         cval[j] = c < CELLS;
         const int cy = c / TXH, cx = c - cy * TXH;
-        cgx[j] = clampi(x0 - 1 + cx, 0, nx - 1);
-        cgy[j] = clampi(y0 - 1 + cy, 0, ny - 1);
+        coff[j] = clampi(x0 - 1 + cx, 0, nx - 1) + nx * clampi(y0 - 1 + cy, 0, ny - 1);
     }
-
-    // pipeline registers: u of a plane being prefetched, gathers of a plane in flight
-    float U[NP][3];
-    float G[NP][8];
-    float fr[NP][3];
-    int base[NP][3];
-    uint32_t occ[NP];
-
-    auto load_u = [&](int p) {
-        const int pz = clampi(p, 0, nz - 1);
+    float pw[NP];
+    uint32_t pf[NP];
+    auto load_plane = [&](int p) {
+        const int base = nxy * clampi(p, 0, nz - 1);
 #pragma unroll
         for (int j = 0; j < NP; ++j)
             if (cval[j]) {
-                const int v = cgx[j] + nx * cgy[j] + nxy * pz;
-                U[j][0] = ux[v];
-                U[j][1] = uy[v];
-                U[j][2] = uz[v];
+                pw[j] = a.wI0[base + coff[j]];
+                pf[j] = masked ? a.F[base + coff[j]] : 0u;
             }
     };
-    auto issue_gathers = [&](int p) {
-        const int pz = clampi(p, 0, nz - 1);
+    auto store_plane = [&](int p) {
+        const int sl = (p - z0 + 1) & 3;
 #pragma unroll
         for (int j = 0; j < NP; ++j)
             if (cval[j]) {
-                const Split sx = split_axis(cgx[j], U[j][0], nx);
-                const Split sy = split_axis(cgy[j], U[j][1], ny);
-                const Split sz = split_axis(pz, U[j][2], nz);
-                const Corners q = corners(sx, sy, sz, nx, nxy);
-                G[j][0] = I0[q.r00 + q.x0];
-                G[j][1] = I0[q.r00 + q.x1];
-                G[j][2] = I0[q.r10 + q.x0];
-                G[j][3] = I0[q.r10 + q.x1];
-                G[j][4] = I0[q.r01 + q.x0];
-                G[j][5] = I0[q.r01 + q.x1];
-                G[j][6] = I0[q.r11 + q.x0];
-                G[j][7] = I0[q.r11 + q.x1];
-                base[j][0] = sx.i0;
-                base[j][1] = sy.i0;
-                base[j][2] = sz.i0;
-                fr[j][0] = q.tx;
-                fr[j][1] = q.ty;
-                fr[j][2] = q.tz;
-                occ[j] = masked ? a.mocc[(sx.i0 >> 3) + a.bnx * ((sy.i0 >> 3) + a.bny * (sz.i0 >> 3))] : 0u;
+                W[sl][tid + j * NT] = pw[j];
+                FB[sl][tid + j * NT] = (uint8_t)pf[j];
             }
     };
-    auto finish_plane = [&](int p) {
-        const int s = (p - z0 + 1) & 3;
-#pragma unroll
-        for (int j = 0; j < NP; ++j)
-            if (cval[j]) {
-                const int c = tid + j * NT;
-                W[s][c] = lerp8(G[j], fr[j][0], fr[j][1], fr[j][2]);
-                uint32_t any = 0;
-                float kv = 0.f;
-                if (occ[j]) {  // a structure is near: mask bits at the 8 corners
-                    const int i0 = base[j][0], j0 = base[j][1], l0 = base[j][2];
-                    const int i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
-                    const uint8_t *__restrict__ mb = a.mbits;
-                    uint32_t b[8];
-                    b[0] = mb[i0 + nx * j0 + nxy * l0];
-                    b[1] = mb[i1 + nx * j0 + nxy * l0];
-                    b[2] = mb[i0 + nx * j1 + nxy * l0];
-                    b[3] = mb[i1 + nx * j1 + nxy * l0];
-                    b[4] = mb[i0 + nx * j0 + nxy * l1];
-                    b[5] = mb[i1 + nx * j0 + nxy * l1];
-                    b[6] = mb[i0 + nx * j1 + nxy * l1];
-                    b[7] = mb[i1 + nx * j1 + nxy * l1];
-                    any = b[0] | b[1] | b[2] | b[3] | b[4] | b[5] | b[6] | b[7];
-                    if (any != 0 && (any & (any - 1)) == 0) {  // one structure: its K_i~ here
-                        float h[8];
-#pragma unroll
-                        for (int m = 0; m < 8; ++m) h[m] = (b[m] & any) ? G[j][m] + a.c0 : 0.f;
-                        kv = lerp8(h, fr[j][0], fr[j][1], fr[j][2]);
-                    }
-                }
-                F[s][c] = (uint8_t)any;
-                K[s][c] = kv;
-            }
-    };
-
-    // prologue: planes z0 - 1, z0, z0 + 1 warped; u of z0 + 2 and the target row of z0 loaded
-    load_u(z0 - 1);
-    issue_gathers(z0 - 1);
-    finish_plane(z0 - 1);
-    load_u(z0);
-    issue_gathers(z0);
-    finish_plane(z0);
-    load_u(z0 + 1);
-    issue_gathers(z0 + 1);
-    finish_plane(z0 + 1);
-    load_u(z0 + 2);
 
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < nx && gy < ny;
@@ -298,18 +291,19 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
             urr = a.partials != nullptr ? a.uroi[v] : 0u;
         }
     };
+
+    load_plane(z0 - 1);
+    store_plane(z0 - 1);
+    load_plane(z0);
+    store_plane(z0);
+    load_plane(z0 + 1);
     load_target(z0);
-    __syncthreads();
 
     for (int z = z0; z < z1; ++z) {
+        store_plane(z + 1);
+        if (z + 2 <= z1) load_plane(z + 2);
+        __syncthreads();
         float dsq = 0.f;
-        // (1) gathers of plane z + 2 and the u of plane z + 3 go in flight
-        const bool ahead = z + 2 <= z1;
-        if (ahead) {
-            issue_gathers(z + 2);
-            if (z + 3 <= z1) load_u(z + 3);
-        }
-        // (2) the step of plane z from the ring (planes z - 1, z, z + 1)
         if (own) {
             const int v = gx + nx * gy + nxy * z;
             const int sm = (z - z0) & 3, s0 = (z - z0 + 1) & 3, sp = (z - z0 + 2) & 3;
@@ -331,16 +325,24 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
                 float den = __builtin_fmaf(d, d, a02);  // beta = d^2 (Thirion)
                 float lam_off = a.lam_sum;
                 if (masked) {
-                    const uint32_t kb = (uint32_t)F[s0][c] | F[s0][c - 1] | F[s0][c + 1] | F[s0][c - TXH] |
-                                        F[s0][c + TXH] | F[sm][c] | F[sp][c] | tb;
+                    const uint32_t fc = FB[s0][c], fxm = FB[s0][c - 1], fxp = FB[s0][c + 1];
+                    const uint32_t fym = FB[s0][c - TXH], fyp = FB[s0][c + TXH], fzm = FB[sm][c], fzp = FB[sp][c];
+                    const uint32_t kb = fc | fxm | fxp | fym | fyp | fzm | fzp | tb;
+                    const int xm = max(gx - 1, 0), xp = min(gx + 1, nx - 1);
+                    const int ym = max(gy - 1, 0), yp = min(gy + 1, ny - 1);
+                    const int zm = max(z - 1, 0), zp = min(z + 1, nz - 1);
                     if (kb != 0 && (kb & (kb - 1)) == 0) {
-                        // one structure i near: every stencil cell holds K_i~ (0 where its
-                        // corners miss the structure), so its terms come from the ring
+                        // one structure i near: K_i~ at each stencil cell from the warp (0
+                        // where the cell's corners miss the structure)
                         const int i = __builtin_ctz(kb);
-                        const float Kc = K[s0][c];
-                        const float gkx = 0.5f * (K[s0][c + 1] - K[s0][c - 1]);
-                        const float gky = 0.5f * (K[s0][c + TXH] - K[s0][c - TXH]);
-                        const float gkz = 0.5f * (K[sp][c] - K[sm][c]);
+                        const float *__restrict__ K = a.K;
+                        const float Kc = fc ? K[v] : 0.f;
+                        const float gkx = 0.5f * ((fxp ? K[xp + nx * gy + nxy * z] : 0.f) -
+                                                  (fxm ? K[xm + nx * gy + nxy * z] : 0.f));
+                        const float gky = 0.5f * ((fyp ? K[gx + nx * yp + nxy * z] : 0.f) -
+                                                  (fym ? K[gx + nx * ym + nxy * z] : 0.f));
+                        const float gkz = 0.5f * ((fzp ? K[gx + nx * gy + nxy * zp] : 0.f) -
+                                                  (fzm ? K[gx + nx * gy + nxy * zm] : 0.f));
                         const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
                         const float ai = __builtin_fmaf(a.hs[i], proj, a0);
                         const float ni = (tb & kb) ? t0 + a.c0 : 0.f;
@@ -354,9 +356,6 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
                     } else if (kb) {  // several structures near: their terms in full
                         lam_off = 0.f;
                         const float tc0 = t0 + a.c0;
-                        const int xm = max(gx - 1, 0), xp = min(gx + 1, nx - 1);
-                        const int ym = max(gy - 1, 0), yp = min(gy + 1, ny - 1);
-                        const int zm = max(z - 1, 0), zp = min(z + 1, nz - 1);
 #pragma unroll 1
                         for (int i = 0; i < a.k; ++i) {
                             const uint32_t bit = 1u << i;
@@ -368,9 +367,9 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
                                     const int px = q == 1 ? xp : (q == 2 ? xm : gx);
                                     const int py = q == 3 ? yp : (q == 4 ? ym : gy);
                                     const int pz = q == 5 ? zp : (q == 6 ? zm : z);
-                                    const float K = warp_masked(a, px, py, pz, bit);
-                                    const float hK = 0.5f * K;
-                                    if (q == 0) Kc = K;
+                                    const float Kq = warp_masked(a, px, py, pz, bit);
+                                    const float hK = 0.5f * Kq;
+                                    if (q == 0) Kc = Kq;
                                     else if (q == 1) gkx = hK;
                                     else if (q == 2) gkx -= hK;
                                     else if (q == 3) gky = hK;
@@ -412,12 +411,8 @@ __device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
             const float r = wave_sum(dsq);
             if (tx == 0) a.partials[(z * ny + gy) * ((nx + kTileX - 1) / kTileX) + x0 / kTileX] = r;
         }
-        // (3) the target row of plane z + 1, then the warped plane z + 2 into the ring
         load_target(z + 1);
-        if (ahead) finish_plane(z + 2);
-        __syncthreads();
     }
-
 }
 
 // number of tiles (blocks) of a volume for a tile of 64 x TY columns and TZ planes
@@ -625,9 +620,17 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
     }
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < nx && gy < ny;
+    // smoothing of u: the warp of I0 with the new u at plane z is issued after the plane's
+    // store and finished after the next plane has been filtered
+    WarpPending wp;
+    int wv = -1;
     for (int z = z0; z < z1; ++z) {
         filter_plane(z + R + 1, z + 1 < z1, COMPOSE ? z + 1 : -1, z + 2 <= z1 ? z + 2 : -1, v3);
         push(v3);
+        if constexpr (!COMPOSE) {
+            if (wv >= 0) warp_finish(a.warp, wp, wv);
+            wv = -1;
+        }
         if (own) {
             const int v = gx + nx * gy + nxy * z;
             float s[3];
@@ -669,8 +672,13 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
             } else {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) a.out[k][v] = s[k];
+                warp_issue(a.warp, gx, gy, z, s[0], s[1], s[2], wp);
+                wv = v;
             }
         }
+    }
+    if constexpr (!COMPOSE) {
+        if (wv >= 0) warp_finish(a.warp, wp, wv);
     }
 }
 
@@ -680,6 +688,20 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
     const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
     const int q = pair_of(b.prefix, b.n, L);
     smooth_tile<R, TY, COMPOSE>(b.d[q], L - b.prefix[q]);
+}
+
+// Warp of the moving image with the field at the start of a level (the smoothing of u
+// produces it for every later iteration).
+__global__ void __launch_bounds__(256) k_warp_init(WarpArgs w, Field3 u)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= w.d.n()) return;
+    const int i = (int)(idx % w.d.nx);
+    const int j = (int)((idx / w.d.nx) % w.d.ny);
+    const int l = (int)(idx / ((int64_t)w.d.nx * w.d.ny));
+    WarpPending p;
+    warp_issue(w, i, j, l, u.p[0][idx], u.p[1][idx], u.p[2][idx], p);
+    warp_finish(w, p, (int)idx);
 }
 
 // ============================================================================
@@ -732,13 +754,6 @@ __global__ void __launch_bounds__(256) k_restrict_pass(const float *__restrict__
     for (int m = 1; m <= R; ++m) s = __builtin_fmaf(t.w[m], at(-m) + at(m), s);
     out[idx] = s;
 }
-
-struct Field3 {
-    const float *p[3];
-};
-struct Field3W {
-    float *p[3];
-};
 
 __global__ void __launch_bounds__(256) k_prolong(Field3 uc, Dims dc, Field3W uf, Dims df)
 {
@@ -1014,6 +1029,13 @@ hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, bool compose, i
     case 16: return smooth_batch_ty<16>(b, radius, compose, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_warp_init(const WarpArgs &w, const float *const u[3], hipStream_t s)
+{
+    Field3 f{{u[0], u[1], u[2]}};
+    hipLaunchKernelGGL(k_warp_init, dim3(blocks_for(w.d.n(), 256)), dim3(256), 0, s, w, f);
+    return hipGetLastError();
 }
 
 hipError_t launch_delta_batch(const DeltaBatch &b, hipStream_t s)

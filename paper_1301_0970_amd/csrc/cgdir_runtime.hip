@@ -165,9 +165,13 @@ size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, 
     const size_t n0 = (size_t)d0.n();
     size_t b = 0;
     b += 3 * align_up(3 * n0 * sizeof(float));  // u, du, uc
+    b += align_up(n0 * sizeof(float));          // warped moving image
     for (int l = 1; l < p.levels; ++l) b += 2 * align_up((size_t)level_dims(d0, l).n() * sizeof(float));
     if (host_images) b += 2 * align_up(n0 * sizeof(float));
-    if (k > 0) b += 2 * align_up(n0) + align_up((size_t)brick_dims(d0).n());  // bit-planes, occupancy
+    if (k > 0) {  // bit-planes, brick occupancy, stencil structure bits, K_i~
+        b += 2 * align_up(n0) + align_up((size_t)brick_dims(d0).n());
+        b += align_up(n0) + align_up(n0 * sizeof(float));
+    }
     if (want_delta(p)) {
         b += align_up(n0);  // UROI
         b += align_up((size_t)metric_parts(d0) * sizeof(float));
@@ -484,6 +488,8 @@ struct Job {
     const float *I0[CGDIR_MAX_LEVELS] = {}, *T0[CGDIR_MAX_LEVELS] = {};
     uint8_t *mbits = nullptr, *tbits = nullptr, *uroi = nullptr, *mocc = nullptr;
     float *ubuf = nullptr, *dubuf = nullptr, *ucbuf = nullptr;
+    float *wI0 = nullptr, *Kbuf = nullptr;
+    uint8_t *Fbuf = nullptr;
     float *partials = nullptr;
     double *delta_dev = nullptr;
     int64_t *misc_i64 = nullptr;  // [0] UROI count, [1..] reduction partials
@@ -552,7 +558,8 @@ struct Job {
         ubuf = (float *)take(3 * n0 * sizeof(float));
         dubuf = (float *)take(3 * n0 * sizeof(float));
         ucbuf = (float *)take(3 * n0 * sizeof(float));
-        bool ok = ubuf && dubuf && ucbuf;
+        wI0 = (float *)take(n0 * sizeof(float));
+        bool ok = ubuf && dubuf && ucbuf && wI0;
         if (host_images) {
             float *a = (float *)take(n0 * sizeof(float));
             float *b = (float *)take(n0 * sizeof(float));
@@ -575,7 +582,9 @@ struct Job {
             mbits = (uint8_t *)take(n0);
             tbits = (uint8_t *)take(n0);
             mocc = (uint8_t *)take((size_t)brick_dims(d0).n());
-            ok = ok && mbits && tbits && mocc;
+            Fbuf = (uint8_t *)take(n0);
+            Kbuf = (float *)take(n0 * sizeof(float));
+            ok = ok && mbits && tbits && mocc && Fbuf && Kbuf;
         }
         if (delta_on) {
             uroi = (uint8_t *)take(n0);
@@ -690,16 +699,43 @@ struct Job {
 
     bool contour_at(int l) const { return k > 0 && ((req.params.contour_level_mask >> l) & 1u); }
 
-    // prolongation into the next finer level (nothing at the coarsest)
+    // the warp of the moving image with this level's field
+    WarpArgs warp_args() const
+    {
+        const Dims d = level_dims(d0, level);
+        const bool contour = contour_at(level);
+        WarpArgs w{};
+        w.I0 = I0[level];
+        w.mbits = contour ? mbits : nullptr;
+        w.mocc = contour ? mocc : nullptr;
+        w.wI0 = wI0;
+        w.F = contour ? Fbuf : nullptr;
+        w.K = contour ? Kbuf : nullptr;
+        w.d = d;
+        const Dims db = brick_dims(d);
+        w.bnx = db.nx;
+        w.bny = db.ny;
+        w.c0 = req.params.intensity_offset;
+        return w;
+    }
+
+    // start of a level: prolongation into it (except at the coarsest), then the warp of
+    // the moving image with the level's first field
     int begin_level()
     {
         level_started = true;
-        if (level == L - 1) return CGDIR_OK;
-        const Dims dc = level_dims(d0, level + 1), df = level_dims(d0, level);
-        const float *uc[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
-        float *uf[3] = {comp(dubuf, 0), comp(dubuf, 1), comp(dubuf, 2)};
-        HIP_TRY(timed(ctx, K_PROLONG * 8 + level, (double)df.n(), [&] { return launch_prolong(uc, dc, uf, df, ctx->stream); }));
-        std::swap(ubuf, dubuf);
+        const Dims df = level_dims(d0, level);
+        if (level < L - 1) {
+            const Dims dc = level_dims(d0, level + 1);
+            const float *uc[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
+            float *uf[3] = {comp(dubuf, 0), comp(dubuf, 1), comp(dubuf, 2)};
+            HIP_TRY(timed(ctx, K_PROLONG * 8 + level, (double)df.n(),
+                          [&] { return launch_prolong(uc, dc, uf, df, ctx->stream); }));
+            std::swap(ubuf, dubuf);
+        }
+        const float *u3[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
+        const WarpArgs w = warp_args();
+        HIP_TRY(timed(ctx, K_WARP * 8 + level, (double)df.n(), [&] { return launch_warp_init(w, u3, ctx->stream); }));
         return CGDIR_OK;
     }
 
@@ -711,20 +747,19 @@ struct Job {
         const Dims d = level_dims(d0, level);
         const bool contour = contour_at(level);
         ForceArgs fa{};
-        fa.I0 = I0[level];
+        fa.wI0 = wI0;
+        fa.F = contour ? Fbuf : nullptr;
+        fa.K = contour ? Kbuf : nullptr;
         fa.T0 = T0[level];
-        fa.mbits = contour ? mbits : nullptr;
         fa.tbits = contour ? tbits : nullptr;
-        fa.mocc = contour ? mocc : nullptr;
-        const Dims db = brick_dims(d);
-        fa.bnx = db.nx;
-        fa.bny = db.ny;
         fa.uroi = metric() ? uroi : nullptr;
-        fa.partials = metric() ? partials : nullptr;
+        fa.I0 = I0[level];
+        fa.mbits = contour ? mbits : nullptr;
         for (int c = 0; c < 3; ++c) {
             fa.u[c] = comp(ubuf, c);
             fa.du[c] = comp(dubuf, c);
         }
+        fa.partials = metric() ? partials : nullptr;
         fa.d = d;
         fa.k = contour ? k : 0;
         fa.lam_sum = 0.f;
@@ -776,6 +811,7 @@ struct Job {
         sb.d = level_dims(d0, level);
         sb.tz = ctx->tune.smooth_tz;
         for (int m = 0; m <= kMaxRadius; ++m) sb.w[m] = wd[m];
+        sb.warp = warp_args();
         return sb;
     }
 

@@ -107,8 +107,9 @@ struct Field3W {
 
 // XCD-aware block order.  The dispatcher hands consecutive block ids to the 8 XCDs in
 // turn; the blocks one XCD receives are mapped onto a contiguous range of logical tiles, so
-// that tiles sharing halo cache lines run on the same L2.  Logical order: z chunk fastest,
-// then x tile, then y tile.  Bijective on [0, total).
+// that tiles sharing halo cache lines run on the same L2.  Logical order: x tile fastest,
+// then y tile, then z chunk, so that the blocks an XCD runs at one time cover a compact
+// patch of neighbouring columns marching through z together.  Bijective on [0, total).
 __device__ __forceinline__ int xcd_logical(int b, int total)
 {
     const int per = total >> 3, rem = total & 7;
@@ -120,16 +121,16 @@ struct TileCoord {
     int x0, y0, z0, z1;
 };
 
-// logical tile L of a volume: z chunk fastest, then x tile, then y tile
+// logical tile L of a volume: x tile fastest, then y tile, then z chunk
 __device__ __forceinline__ TileCoord tile_of(int ty_rows, int tz, const Dims &d, int L)
 {
     const int ntx = (d.nx + kTileX - 1) / kTileX;
-    const int nzc = (d.nz + tz - 1) / tz;
-    const int zc = L % nzc, t = L / nzc;
+    const int nty = (d.ny + ty_rows - 1) / ty_rows;
+    const int tx = L % ntx, t = L / ntx;
     TileCoord c;
-    c.x0 = (t % ntx) * kTileX;
-    c.y0 = (t / ntx) * ty_rows;
-    c.z0 = zc * tz;
+    c.x0 = tx * kTileX;
+    c.y0 = (t % nty) * ty_rows;
+    c.z0 = (t / nty) * tz;
     c.z1 = min(c.z0 + tz, d.nz);
     return c;
 }

@@ -196,8 +196,9 @@ const char *kKernelNames[K_COUNT] = {"force", "smooth_compose", "smooth", "delta
 struct TileCfg {
     int ty, tz;
 };
-const TileCfg kForceCands[] = {{4, 8}, {4, 4}, {4, 16}, {8, 8}, {8, 16}, {16, 8}};
-const TileCfg kSmoothCands[] = {{8, 32}, {8, 16}, {16, 32}, {16, 16}, {4, 16}, {8, 8}, {4, 32}};
+const TileCfg kForceCands[] = {{4, 16}, {4, 4}, {4, 8}, {4, 32}, {8, 16}, {8, 32}, {8, 128}, {16, 16}, {16, 128}};
+const TileCfg kSmoothCands[] = {{8, 32}, {8, 8}, {8, 16}, {8, 64}, {8, 128}, {16, 16}, {16, 32}, {16, 64},
+                                {16, 128}, {4, 16}, {4, 64}};
 
 class Tuner {
   public:
@@ -223,8 +224,12 @@ class Tuner {
             e.best = 0;
             for (int i = 1; i < nc; ++i)
                 if (e.ms[i] < e.ms[e.best]) e.best = i;
-            if (log) std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.4f ms)\n", key.c_str(), c[e.best].ty,
-                                  c[e.best].tz, e.ms[e.best]);
+            if (log) {
+                std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.4f ms) |", key.c_str(), c[e.best].ty,
+                             c[e.best].tz, e.ms[e.best]);
+                for (int i = 0; i < nc; ++i) std::fprintf(stderr, " %d,%d:%.4f", c[i].ty, c[i].tz, e.ms[i]);
+                std::fprintf(stderr, "\n");
+            }
             return c[e.best];
         }
         if (e.next < nc) {

@@ -7,7 +7,7 @@ already resident in HBM.  value = voxel-iterations per second, sum over levels o
 (voxels x iterations) / wall time per step.
 
 Also reported on the same JSON line:
-  roofline      the dominant kernel (finest-level force) -- algorithmic bytes per launch
+  roofline      the dominant kernel (finest-level step or smooth) -- algorithmic bytes per launch
                 (bytes per voxel x voxels) over its average launch duration, from HIP
                 events on the library's stream during a profiled pass of the same steps;
                 traffic = HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -29,11 +29,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # algorithmic bytes per voxel of each finest-level kernel (fields FP32 SoA, mask bit-planes
-# one byte per voxel per side): force reads u (12), I0 (4, gathered about once), T0 (4), the
-# two bit-planes (2) and writes du (12); smooth_compose reads du (12), u (12, gathered near
-# x) and writes u_c (12); smooth reads u_c (12) and writes u (12).
-BYTES_PER_VOXEL = {"force": 34, "smooth_compose": 36, "smooth": 24}
-KERNEL_SYMBOL = {"force": "k_force", "smooth_compose": "k_smooth", "smooth": "k_smooth"}
+# one byte per voxel per side).  step (force, fluid smoothing, compose) reads the warped
+# image I0~ (4), T0 (4), u (12) and, with contour terms, the stencil structure bits and the
+# target bits (1 + 1), and, with the stopping metric, the UROI (1); it writes u_c (12).
+# smooth (diffusion smoothing, then the warp of I0) reads u_c (12) and I0 (4, gathered about
+# once) and writes u (12), I0~ (4) and, with contour terms, the structure bits (1).  The
+# K_i~ values and moving-mask bits near structures are data dependent and left out.
+def bytes_per_voxel(kernel, k, metric):
+    if kernel == "step":
+        return 4 + 4 + 12 + 12 + (2 if k else 0) + (1 if metric else 0)
+    if kernel == "smooth":
+        return 12 + 4 + 12 + 4 + (1 if k else 0)
+    return None
+
+
+KERNEL_SYMBOL = {"step": "k_step_batch", "smooth": "k_smooth_batch"}
 
 WORKLOADS = {
     "pelvis": ("pelvis-like CT 512x512x128, 8 structures (+15 HU), 3 levels x 150 iterations, "
@@ -234,9 +244,9 @@ def main():
         torch.cuda.synchronize()
         stats = ctx.kernel_stats()
     finest = {s["name"].split("@")[0]: s for s in stats if s["name"].endswith("@L0")}
-    dom = max((n for n in finest if n in BYTES_PER_VOXEL), key=lambda n: finest[n]["total_ms"])
+    dom = max((n for n in finest if n in KERNEL_SYMBOL), key=lambda n: finest[n]["total_ms"])
     s = finest[dom]
-    bpv = BYTES_PER_VOXEL[dom] - (2 if dom == "force" and pair.k == 0 else 0)
+    bpv = bytes_per_voxel(dom, pair.k, prm.stop_mode != 0)
     per_launch_bytes = bpv * s["voxels"] / s["launches"]
     avg_ms = s["total_ms"] / s["launches"]
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9

@@ -34,19 +34,20 @@ struct WarpArgs {
     float c0;                 // CT-number offset
 };
 
-// Arguments of the force kernel (gradient, Eq.7, stopping-metric partials) on the warped
-// image of the current field.
-struct ForceArgs {
+// Arguments of the step kernel: the force (gradient, Eq.7) on the warped image of the
+// current field, its smoothing with sigma_fluid, the composite update u_c = s + u o (Id + s)
+// with s the smoothed step, and the stopping-metric partials.
+struct StepArgs {
     const float *wI0;         // I0~ of the current field
     const uint8_t *F;         // stencil structure bits (null: k = 0 at this level)
     const float *K;           // K_i~ where F has one bit
     const float *T0;          // target image at this level
     const uint8_t *tbits;     // bit i = voxel inside structure i on the target image
     const uint8_t *uroi;      // stopping region (or null: no metric)
-    const float *I0;          // moving image, mask bits and field: re-warp where several
+    const float *I0;          // moving image and mask bits: re-warp where several
     const uint8_t *mbits;     //   structures meet in one stencil
-    const float *u[3];
-    float *du[3];             // output step
+    const float *u[3];        // current field
+    float *uc[3];             // output: composite update
     float *partials;          // sums of ((T0 - I0~)/norm)^2 over the UROI, one per 64-voxel
                               // row segment: index (z * ny + y) * ceil(nx / 64) + x / 64
     Dims d;
@@ -56,19 +57,19 @@ struct ForceArgs {
     float hs[kMaxStructs];    // s_i / 2
     float c0;                 // CT-number offset
     float inv_norm;           // 1 / norm_range
+    float w[kMaxRadius + 1];  // fluid Gaussian: w[0] centre, w[m] = weight at +-m
     int tz;                   // planes per block (z chunk)
 };
 
-// Arguments of the separable Gaussian kernels: smoothing of du followed by the composite
-// update (compose), or smoothing of u_c into u followed by the warp of I0 with that u.
+// Arguments of the smoothing of u_c into u (diffusion Gaussian), followed by the warp of I0
+// with the new u.
 struct SmoothArgs {
     const float *in[3];
-    const float *u[3];        // compose: the field gathered at x + smoothed(in)
     float *out[3];
     Dims d;
     float w[kMaxRadius + 1];  // w[0] centre, w[m] = weight at +-m
     int tz;
-    WarpArgs warp;            // smoothing of u: where the warp goes
+    WarpArgs warp;            // where the warp goes
 };
 
 // One pair's stopping-metric reduction in a batched finalize.
@@ -82,11 +83,11 @@ struct DeltaJob {
 // Batched launches: one launch over the tiles of n pairs.  The descriptors travel in the
 // kernel-argument segment (<= 4 KiB), so a launch holds a bounded number of pairs.
 // prefix[q] = first block of pair q, prefix[n] = total blocks.
-constexpr int kBatchForce = 16, kBatchSmooth = 20, kBatchDelta = 64;
-struct ForceBatch {
+constexpr int kBatchStep = 16, kBatchSmooth = 20, kBatchDelta = 64;
+struct StepBatch {
     int n;
-    int prefix[kBatchForce + 1];
-    ForceArgs d[kBatchForce];
+    int prefix[kBatchStep + 1];
+    StepArgs d[kBatchStep];
 };
 struct SmoothBatch {
     int n;
@@ -97,12 +98,12 @@ struct DeltaBatch {
     int n;
     DeltaJob d[kBatchDelta];
 };
-static_assert(sizeof(ForceBatch) <= 4096 && sizeof(SmoothBatch) <= 4096 && sizeof(DeltaBatch) <= 4096,
+static_assert(sizeof(StepBatch) <= 4096 && sizeof(SmoothBatch) <= 4096 && sizeof(DeltaBatch) <= 4096,
               "kernel arguments are limited to 4 KiB");
 
 // ---- launchers (cgdir_kernels.hip); each returns the hipError_t of its launch -------
-hipError_t launch_force_batch(const ForceBatch &b, int ty, hipStream_t s);
-hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, bool compose, int ty, hipStream_t s);
+hipError_t launch_step_batch(const StepBatch &b, int radius, int ty, hipStream_t s);
+hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, int ty, hipStream_t s);
 hipError_t launch_delta_batch(const DeltaBatch &b, hipStream_t s);
 hipError_t launch_warp_init(const WarpArgs &w, const float *const u[3], hipStream_t s);
 int tile_blocks(Dims d, int ty, int tz);

@@ -16,6 +16,20 @@ __device__ __forceinline__ float lerpf(float a, float b, float t) { return __bui
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// Loads and stores at an element index.  A volume holds at most 2^30 voxels, so a byte
+// offset fits in 32 bits and the address is a scalar base plus a 32-bit vector offset: no
+// 64-bit address arithmetic per access.
+template <class T>
+__device__ __forceinline__ T ldg(const T *base, uint32_t i)
+{
+    return *(const T *)((const char *)base + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void stg(T *base, uint32_t i, T v)
+{
+    *(T *)((char *)base + i * (uint32_t)sizeof(T)) = v;
+}
+
 // Sample coordinate p = i + u on an axis of n voxels, clamped to [0, n-1] (trilinear
 // interpolation with replicated borders): base index, successor and fraction.  The
 // coordinate is split into integer and fractional parts so that i + u is never rounded.
@@ -80,14 +94,14 @@ __device__ __forceinline__ float lerp8(const float f[8], float tx, float ty, flo
 __device__ __forceinline__ float trilinear(const float *__restrict__ f, const Corners &c)
 {
     float v[8];
-    v[0] = f[c.r00 + c.x0];
-    v[1] = f[c.r00 + c.x1];
-    v[2] = f[c.r10 + c.x0];
-    v[3] = f[c.r10 + c.x1];
-    v[4] = f[c.r01 + c.x0];
-    v[5] = f[c.r01 + c.x1];
-    v[6] = f[c.r11 + c.x0];
-    v[7] = f[c.r11 + c.x1];
+    v[0] = ldg(f, c.r00 + c.x0);
+    v[1] = ldg(f, c.r00 + c.x1);
+    v[2] = ldg(f, c.r10 + c.x0);
+    v[3] = ldg(f, c.r10 + c.x1);
+    v[4] = ldg(f, c.r01 + c.x0);
+    v[5] = ldg(f, c.r01 + c.x1);
+    v[6] = ldg(f, c.r11 + c.x0);
+    v[7] = ldg(f, c.r11 + c.x1);
     return lerp8(v, c.tx, c.ty, c.tz);
 }
 
@@ -137,17 +151,17 @@ __device__ __forceinline__ TileCoord tile_of(int ty_rows, int tz, const Dims &d,
 
 // Warp of the masked moving image m_i (I0 + c0) at voxel (px, py, pz) with the field u:
 // K_i~ of the decomposition below, for the structures selected by `bit`.
-__device__ __forceinline__ float warp_masked(const ForceArgs &a, int px, int py, int pz, uint32_t bit)
+__device__ __forceinline__ float warp_masked(const StepArgs &a, int px, int py, int pz, uint32_t bit)
 {
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
     const int v = px + nx * py + nxy * pz;
-    const Corners q = corners(split_axis(px, a.u[0][v], nx), split_axis(py, a.u[1][v], ny),
-                              split_axis(pz, a.u[2][v], nz), nx, nxy);
+    const Corners q = corners(split_axis(px, ldg(a.u[0], v), nx), split_axis(py, ldg(a.u[1], v), ny),
+                              split_axis(pz, ldg(a.u[2], v), nz), nx, nxy);
     const int o[8] = {q.r00 + q.x0, q.r00 + q.x1, q.r10 + q.x0, q.r10 + q.x1,
                       q.r01 + q.x0, q.r01 + q.x1, q.r11 + q.x0, q.r11 + q.x1};
     float h[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) h[j] = (a.mbits[o[j]] & bit) ? a.I0[o[j]] + a.c0 : 0.f;
+    for (int j = 0; j < 8; ++j) h[j] = (ldg(a.mbits, o[j]) & bit) ? ldg(a.I0, o[j]) + a.c0 : 0.f;
     return lerp8(h, q.tx, q.ty, q.tz);
 }
 
@@ -171,26 +185,26 @@ __device__ __forceinline__ void warp_issue(const WarpArgs &w, int gx, int gy, in
     const Split sx = split_axis(gx, ux, nx), sy = split_axis(gy, uy, ny), sz = split_axis(gz, uz, nz);
     const Corners q = corners(sx, sy, sz, nx, nxy);
     const float *__restrict__ I0 = w.I0;
-    p.g[0] = I0[q.r00 + q.x0];
-    p.g[1] = I0[q.r00 + q.x1];
-    p.g[2] = I0[q.r10 + q.x0];
-    p.g[3] = I0[q.r10 + q.x1];
-    p.g[4] = I0[q.r01 + q.x0];
-    p.g[5] = I0[q.r01 + q.x1];
-    p.g[6] = I0[q.r11 + q.x0];
-    p.g[7] = I0[q.r11 + q.x1];
+    p.g[0] = ldg(I0, q.r00 + q.x0);
+    p.g[1] = ldg(I0, q.r00 + q.x1);
+    p.g[2] = ldg(I0, q.r10 + q.x0);
+    p.g[3] = ldg(I0, q.r10 + q.x1);
+    p.g[4] = ldg(I0, q.r01 + q.x0);
+    p.g[5] = ldg(I0, q.r01 + q.x1);
+    p.g[6] = ldg(I0, q.r11 + q.x0);
+    p.g[7] = ldg(I0, q.r11 + q.x1);
     p.t[0] = q.tx;
     p.t[1] = q.ty;
     p.t[2] = q.tz;
     p.b[0] = sx.i0;
     p.b[1] = sy.i0;
     p.b[2] = sz.i0;
-    p.occ = w.mbits != nullptr ? w.mocc[(sx.i0 >> 3) + w.bnx * ((sy.i0 >> 3) + w.bny * (sz.i0 >> 3))] : 0u;
+    p.occ = w.mbits != nullptr ? ldg(w.mocc, (sx.i0 >> 3) + w.bnx * ((sy.i0 >> 3) + w.bny * (sz.i0 >> 3))) : 0u;
 }
 
 __device__ __forceinline__ void warp_finish(const WarpArgs &w, const WarpPending &p, int v)
 {
-    w.wI0[v] = lerp8(p.g, p.t[0], p.t[1], p.t[2]);
+    stg(w.wI0, v, lerp8(p.g, p.t[0], p.t[1], p.t[2]));
     if (w.mbits == nullptr) return;
     uint32_t any = 0;
     if (p.occ) {  // a structure is near: mask bits at the 8 corners
@@ -199,31 +213,27 @@ __device__ __forceinline__ void warp_finish(const WarpArgs &w, const WarpPending
         const int i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
         const uint8_t *__restrict__ mb = w.mbits;
         uint32_t b[8];
-        b[0] = mb[i0 + nx * j0 + nxy * l0];
-        b[1] = mb[i1 + nx * j0 + nxy * l0];
-        b[2] = mb[i0 + nx * j1 + nxy * l0];
-        b[3] = mb[i1 + nx * j1 + nxy * l0];
-        b[4] = mb[i0 + nx * j0 + nxy * l1];
-        b[5] = mb[i1 + nx * j0 + nxy * l1];
-        b[6] = mb[i0 + nx * j1 + nxy * l1];
-        b[7] = mb[i1 + nx * j1 + nxy * l1];
+        b[0] = ldg(mb, i0 + nx * j0 + nxy * l0);
+        b[1] = ldg(mb, i1 + nx * j0 + nxy * l0);
+        b[2] = ldg(mb, i0 + nx * j1 + nxy * l0);
+        b[3] = ldg(mb, i1 + nx * j1 + nxy * l0);
+        b[4] = ldg(mb, i0 + nx * j0 + nxy * l1);
+        b[5] = ldg(mb, i1 + nx * j0 + nxy * l1);
+        b[6] = ldg(mb, i0 + nx * j1 + nxy * l1);
+        b[7] = ldg(mb, i1 + nx * j1 + nxy * l1);
         any = b[0] | b[1] | b[2] | b[3] | b[4] | b[5] | b[6] | b[7];
         if (any != 0 && (any & (any - 1)) == 0) {  // one structure: its K_i~ here
             float h[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) h[m] = (b[m] & any) ? p.g[m] + w.c0 : 0.f;
-            w.K[v] = lerp8(h, p.t[0], p.t[1], p.t[2]);
+            stg(w.K, v, lerp8(h, p.t[0], p.t[1], p.t[2]));
         }
     }
-    w.F[v] = (uint8_t)any;
+    stg(w.F, v, (uint8_t)any);
 }
 
 // ============================================================================
-// Force: kernels 2 (gradient) and 3 (moving vector, Eq.7) on the warped moving image.
-// A block owns a 64 x TY column tile and marches through a chunk of z planes; each plane
-// of I0~ and of the stencil structure bits (tile + 1-voxel halo) is prefetched into
-// registers one plane ahead and stored into a 4-slot LDS ring, from which the central
-// differences are taken (one barrier per plane).
+// Eq.7 at one voxel (kernels 2 and 3 on the warped moving image).
 //
 // With s_i the sign of structure i (M_i = s_i m_i, N_i = s_i n_i), the modified images of
 // Eq.2 decompose exactly (trilinear interpolation and central differences are linear):
@@ -233,187 +243,98 @@ __device__ __forceinline__ void warp_finish(const WarpArgs &w, const WarpPending
 // Eq.7 reduce to lambda_i a0 d (numerator) and lambda_i a0^2 (denominator): that is the
 // whole computation for most voxels.  Where one structure touches it, K_i~ at the stencil
 // cells comes from the warp; where several do, K_i~ is re-evaluated from the field.
+//
+// w: I0~ at the voxel and its six clamped neighbours (centre, -x, +x, -y, +y, -z, +z);
+// f: their stencil structure bits (zero when the level has no contour terms).
 // ============================================================================
-template <int TY>
-__device__ __forceinline__ void force_tile(const ForceArgs &a, int L)
+__device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], const uint32_t f[7], float t0,
+                                         uint32_t tb, int gx, int gy, int gz, float du[3], float *dout)
 {
-    constexpr int TXH = kTileX + 2, CELLS = TXH * (TY + 2), NT = kTileX * TY;
-    constexpr int NP = (CELLS + NT - 1) / NT;
-    __shared__ float W[4][CELLS];     // ring of I0~ planes, slot (p - z0 + 1) & 3
-    __shared__ uint8_t FB[4][CELLS];  // stencil structure bits
-
-    const int tid = threadIdx.x;
-    const int tx = tid % kTileX, ty = tid / kTileX;
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
-    const TileCoord tc = tile_of(TY, a.tz, a.d, L);
-    const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
-    const bool masked = a.F != nullptr;
-
-    int coff[NP];
-    bool cval[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const int c = tid + j * NT;
-        cval[j] = c < CELLS;
-        const int cy = c / TXH, cx = c - cy * TXH;
-        coff[j] = clampi(x0 - 1 + cx, 0, nx - 1) + nx * clampi(y0 - 1 + cy, 0, ny - 1);
-    }
-    float pw[NP];
-    uint32_t pf[NP];
-    auto load_plane = [&](int p) {
-        const int base = nxy * clampi(p, 0, nz - 1);
-#pragma unroll
-        for (int j = 0; j < NP; ++j)
-            if (cval[j]) {
-                pw[j] = a.wI0[base + coff[j]];
-                pf[j] = masked ? a.F[base + coff[j]] : 0u;
-            }
-    };
-    auto store_plane = [&](int p) {
-        const int sl = (p - z0 + 1) & 3;
-#pragma unroll
-        for (int j = 0; j < NP; ++j)
-            if (cval[j]) {
-                W[sl][tid + j * NT] = pw[j];
-                FB[sl][tid + j * NT] = (uint8_t)pf[j];
-            }
-    };
-
-    const int gx = x0 + tx, gy = y0 + ty;
-    const bool own = gx < nx && gy < ny;
-    const int c = (ty + 1) * TXH + (tx + 1);
-    float t0r = 0.f;
-    uint32_t tbr = 0, urr = 0;
-    auto load_target = [&](int z) {
-        if (own && z < z1) {
-            const int v = gx + nx * gy + nxy * z;
-            t0r = a.T0[v];
-            tbr = masked ? a.tbits[v] : 0u;
-            urr = a.partials != nullptr ? a.uroi[v] : 0u;
-        }
-    };
-
-    load_plane(z0 - 1);
-    store_plane(z0 - 1);
-    load_plane(z0);
-    store_plane(z0);
-    load_plane(z0 + 1);
-    load_target(z0);
-
-    for (int z = z0; z < z1; ++z) {
-        store_plane(z + 1);
-        if (z + 2 <= z1) load_plane(z + 2);
-        __syncthreads();
-        float dsq = 0.f;
-        if (own) {
-            const int v = gx + nx * gy + nxy * z;
-            const int sm = (z - z0) & 3, s0 = (z - z0 + 1) & 3, sp = (z - z0 + 2) & 3;
-            const float Ic = W[s0][c];
-            const float g0x = 0.5f * (W[s0][c + 1] - W[s0][c - 1]);
-            const float g0y = 0.5f * (W[s0][c + TXH] - W[s0][c - TXH]);
-            const float g0z = 0.5f * (W[sp][c] - W[sm][c]);
-            const float t0 = t0r;
-            const uint32_t tb = tbr;
-            const bool in_uroi = urr != 0;
-            const float d = t0 - Ic;
-            const float a02 = __builtin_fmaf(g0z, g0z, __builtin_fmaf(g0y, g0y, g0x * g0x));
-            float dx = 0.f, dy = 0.f, dz = 0.f;
-            if (a02 != 0.f) {  // n = grad I0~ / |grad I0~| undefined at 0: no step
-                const float a0 = sqrtf(a02);
-                const float inv = 1.0f / a0;
-                const float nxv = g0x * inv, nyv = g0y * inv, nzv = g0z * inv;
-                float num = a0 * d;
-                float den = __builtin_fmaf(d, d, a02);  // beta = d^2 (Thirion)
-                float lam_off = a.lam_sum;
-                if (masked) {
-                    const uint32_t fc = FB[s0][c], fxm = FB[s0][c - 1], fxp = FB[s0][c + 1];
-                    const uint32_t fym = FB[s0][c - TXH], fyp = FB[s0][c + TXH], fzm = FB[sm][c], fzp = FB[sp][c];
-                    const uint32_t kb = fc | fxm | fxp | fym | fyp | fzm | fzp | tb;
-                    const int xm = max(gx - 1, 0), xp = min(gx + 1, nx - 1);
-                    const int ym = max(gy - 1, 0), yp = min(gy + 1, ny - 1);
-                    const int zm = max(z - 1, 0), zp = min(z + 1, nz - 1);
-                    if (kb != 0 && (kb & (kb - 1)) == 0) {
-                        // one structure i near: K_i~ at each stencil cell from the warp (0
-                        // where the cell's corners miss the structure)
-                        const int i = __builtin_ctz(kb);
-                        const float *__restrict__ K = a.K;
-                        const float Kc = fc ? K[v] : 0.f;
-                        const float gkx = 0.5f * ((fxp ? K[xp + nx * gy + nxy * z] : 0.f) -
-                                                  (fxm ? K[xm + nx * gy + nxy * z] : 0.f));
-                        const float gky = 0.5f * ((fyp ? K[gx + nx * yp + nxy * z] : 0.f) -
-                                                  (fym ? K[gx + nx * ym + nxy * z] : 0.f));
-                        const float gkz = 0.5f * ((fzp ? K[gx + nx * gy + nxy * zp] : 0.f) -
-                                                  (fzm ? K[gx + nx * gy + nxy * zm] : 0.f));
-                        const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
-                        const float ai = __builtin_fmaf(a.hs[i], proj, a0);
-                        const float ni = (tb & kb) ? t0 + a.c0 : 0.f;
-                        const float di = __builtin_fmaf(a.hs[i], ni - Kc, d);
-                        const float la = a.lam[i] * ai;
-                        num = __builtin_fmaf(la, di, num);
-                        den = __builtin_fmaf(la, ai, den);
-                        lam_off = 0.f;
-                        for (int j = 0; j < a.k; ++j)
-                            if (j != i) lam_off += a.lam[j];
-                    } else if (kb) {  // several structures near: their terms in full
-                        lam_off = 0.f;
-                        const float tc0 = t0 + a.c0;
+    const float g0x = 0.5f * (w[2] - w[1]);
+    const float g0y = 0.5f * (w[4] - w[3]);
+    const float g0z = 0.5f * (w[6] - w[5]);
+    const float d = t0 - w[0];
+    *dout = d;
+    const float a02 = __builtin_fmaf(g0z, g0z, __builtin_fmaf(g0y, g0y, g0x * g0x));
+    du[0] = du[1] = du[2] = 0.f;
+    // n = grad I0~ / |grad I0~| undefined at 0: no step (also below the smallest normal
+    // float, where the step is below 1e-19 voxel; NaN goes on and is reported)
+    if (a02 < 1.17549435e-38f) return;
+    const float inv = __builtin_amdgcn_rsqf(a02);  // hardware 1/sqrt, ~1 ulp
+    const float a0 = a02 * inv;
+    const float nxv = g0x * inv, nyv = g0y * inv, nzv = g0z * inv;
+    float num = a0 * d;
+    float den = __builtin_fmaf(d, d, a02);  // beta = d^2 (Thirion)
+    float lam_off = a.lam_sum;
+    const uint32_t kb = f[0] | f[1] | f[2] | f[3] | f[4] | f[5] | f[6] | tb;
+    if (kb) {
+        const int xm = max(gx - 1, 0), xp = min(gx + 1, nx - 1);
+        const int ym = max(gy - 1, 0), yp = min(gy + 1, ny - 1);
+        const int zm = max(gz - 1, 0), zp = min(gz + 1, nz - 1);
+        if ((kb & (kb - 1)) == 0) {
+            // one structure i near: K_i~ at each stencil cell from the warp (0 where the
+            // cell's corners miss the structure)
+            const int i = __builtin_ctz(kb);
+            const float *__restrict__ K = a.K;
+            const int v = gx + nx * gy + nxy * gz;
+            const float Kc = f[0] ? ldg(K, v) : 0.f;
+            const float gkx = 0.5f * ((f[2] ? ldg(K, xp + nx * gy + nxy * gz) : 0.f) - (f[1] ? ldg(K, xm + nx * gy + nxy * gz) : 0.f));
+            const float gky = 0.5f * ((f[4] ? ldg(K, gx + nx * yp + nxy * gz) : 0.f) - (f[3] ? ldg(K, gx + nx * ym + nxy * gz) : 0.f));
+            const float gkz = 0.5f * ((f[6] ? ldg(K, gx + nx * gy + nxy * zp) : 0.f) - (f[5] ? ldg(K, gx + nx * gy + nxy * zm) : 0.f));
+            const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
+            const float ai = __builtin_fmaf(a.hs[i], proj, a0);
+            const float ni = (tb & kb) ? t0 + a.c0 : 0.f;
+            const float di = __builtin_fmaf(a.hs[i], ni - Kc, d);
+            const float la = a.lam[i] * ai;
+            num = __builtin_fmaf(la, di, num);
+            den = __builtin_fmaf(la, ai, den);
+            lam_off = 0.f;
+            for (int j = 0; j < a.k; ++j)
+                if (j != i) lam_off += a.lam[j];
+        } else {  // several structures near: their terms in full
+            lam_off = 0.f;
+            const float tc0 = t0 + a.c0;
 #pragma unroll 1
-                        for (int i = 0; i < a.k; ++i) {
-                            const uint32_t bit = 1u << i;
-                            if (kb & bit) {
-                                // K_i~ at the centre and the six clamped neighbours
-                                float Kc = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
+            for (int i = 0; i < a.k; ++i) {
+                const uint32_t bit = 1u << i;
+                if (kb & bit) {
+                    // K_i~ at the centre and the six clamped neighbours
+                    float Kc = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
 #pragma unroll 1
-                                for (int q = 0; q < 7; ++q) {
-                                    const int px = q == 1 ? xp : (q == 2 ? xm : gx);
-                                    const int py = q == 3 ? yp : (q == 4 ? ym : gy);
-                                    const int pz = q == 5 ? zp : (q == 6 ? zm : z);
-                                    const float Kq = warp_masked(a, px, py, pz, bit);
-                                    const float hK = 0.5f * Kq;
-                                    if (q == 0) Kc = Kq;
-                                    else if (q == 1) gkx = hK;
-                                    else if (q == 2) gkx -= hK;
-                                    else if (q == 3) gky = hK;
-                                    else if (q == 4) gky -= hK;
-                                    else if (q == 5) gkz = hK;
-                                    else gkz -= hK;
-                                }
-                                const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
-                                const float ai = __builtin_fmaf(a.hs[i], proj, a0);
-                                const float ni = (tb & bit) ? tc0 : 0.f;
-                                const float di = __builtin_fmaf(a.hs[i], ni - Kc, d);
-                                const float la = a.lam[i] * ai;
-                                num = __builtin_fmaf(la, di, num);
-                                den = __builtin_fmaf(la, ai, den);
-                            } else {
-                                lam_off += a.lam[i];
-                            }
-                        }
+                    for (int q = 0; q < 7; ++q) {
+                        const int px = q == 1 ? xp : (q == 2 ? xm : gx);
+                        const int py = q == 3 ? yp : (q == 4 ? ym : gy);
+                        const int pz = q == 5 ? zp : (q == 6 ? zm : gz);
+                        const float Kq = warp_masked(a, px, py, pz, bit);
+                        const float hK = 0.5f * Kq;
+                        if (q == 0) Kc = Kq;
+                        else if (q == 1) gkx = hK;
+                        else if (q == 2) gkx -= hK;
+                        else if (q == 3) gky = hK;
+                        else if (q == 4) gky -= hK;
+                        else if (q == 5) gkz = hK;
+                        else gkz -= hK;
                     }
+                    const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
+                    const float ai = __builtin_fmaf(a.hs[i], proj, a0);
+                    const float ni = (tb & bit) ? tc0 : 0.f;
+                    const float di = __builtin_fmaf(a.hs[i], ni - Kc, d);
+                    const float la = a.lam[i] * ai;
+                    num = __builtin_fmaf(la, di, num);
+                    den = __builtin_fmaf(la, ai, den);
+                } else {
+                    lam_off += a.lam[i];
                 }
-                num = __builtin_fmaf(lam_off * a0, d, num);
-                den = __builtin_fmaf(lam_off, a02, den);
-                const float vv = num / den;
-                dx = vv * nxv;
-                dy = vv * nyv;
-                dz = vv * nzv;
-            }
-            a.du[0][v] = dx;
-            a.du[1][v] = dy;
-            a.du[2][v] = dz;
-            if (in_uroi) {
-                const float e = d * a.inv_norm;
-                dsq = e * e;
             }
         }
-        // stopping metric: one partial per 64-voxel row segment (a wave is one tile row),
-        // a grouping that does not depend on the launch geometry
-        if (a.partials != nullptr && gy < ny) {
-            const float r = wave_sum(dsq);
-            if (tx == 0) a.partials[(z * ny + gy) * ((nx + kTileX - 1) / kTileX) + x0 / kTileX] = r;
-        }
-        load_target(z + 1);
     }
+    num = __builtin_fmaf(lam_off * a0, d, num);
+    den = __builtin_fmaf(lam_off, a02, den);
+    const float vv = num * __builtin_amdgcn_rcpf(den);  // hardware reciprocal, ~1 ulp
+    du[0] = vv * nxv;
+    du[1] = vv * nyv;
+    du[2] = vv * nzv;
 }
 
 // number of tiles (blocks) of a volume for a tile of 64 x TY columns and TZ planes
@@ -436,13 +357,6 @@ __device__ __forceinline__ int pair_of(const int *prefix, int n, int L)
 
 // one launch over the tiles of several pairs (each pair at its own level and size); the
 // pair descriptors travel in the kernel-argument segment and are read with scalar loads
-template <int TY>
-__global__ void __launch_bounds__(kTileX *TY) k_force_batch(ForceBatch b)
-{
-    const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
-    const int q = pair_of(b.prefix, b.n, L);
-    force_tile<TY>(b.d[q], L - b.prefix[q]);
-}
 
 // Moving-mask occupancy of 8x8x8 bricks: OR of the mask bits over the brick grown by one
 // voxel on its high side, so that a trilinear stencil whose base corner lies in the brick
@@ -462,22 +376,20 @@ __global__ void __launch_bounds__(256) k_brick_occupancy(const uint8_t *__restri
 }
 
 // ============================================================================
-// Separable Gaussian (kernel 1), sampled, radius R = ceil(3 sigma), normalised, clamped
-// indices.  A block owns a 64 x TY column tile: each z plane (tile + R halo) is staged in
-// LDS, filtered along x then y, and pushed into a register ring of 2R+1 planes that the
-// z pass reads.  COMPOSE adds the composite update of kernel 4 on the smoothed step:
-// out(x) = s(x) + u(x + s(x)) per component (u gathered trilinearly).
+// Separable Gaussian (kernel 1) of u_c into u, sampled, radius R = ceil(3 sigma),
+// normalised, clamped indices, followed by the warp of the moving image with the new u
+// (kernel 4 on images).  A block owns a 64 x TY column tile: each z plane (tile + R halo)
+// is staged in LDS, filtered along x then y, and pushed into a register ring of 2R+1
+// planes that the z pass reads.  The warp of plane z is issued after its store and
+// finished after the next plane has been filtered, so its gathers overlap the filtering.
 // ============================================================================
-template <int R, int TY, bool COMPOSE>
+template <int R, int TY>
 __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
 {
     constexpr int WD = kTileX + 2 * R, HT = TY + 2 * R, NT = kTileX * TY;
     constexpr int CELLS = HT * WD, NP = (CELLS + NT - 1) / NT;
-    constexpr int UW = kTileX + 2, UH = TY + 2, UCELLS = UW * UH, NU = (UCELLS + NT - 1) / NT;
-    constexpr int US = COMPOSE ? 3 : 1;
     __shared__ float raw[3][HT][WD];
     __shared__ float xs[3][HT][kTileX];
-    __shared__ float Us[3][US][COMPOSE ? UCELLS : 1];  // compose: u planes z-1..z+1, ring slot (p - z0 + 1) % 3
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
@@ -508,54 +420,14 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
 #pragma unroll
         for (int j = 0; j < NP; ++j)
             if (tid + j * NT < CELLS) {
-                pre[j][0] = in0[base + coff[j]];
-                pre[j][1] = in1[base + coff[j]];
-                pre[j][2] = in2[base + coff[j]];
+                pre[j][0] = ldg(in0, base + coff[j]);
+                pre[j][1] = ldg(in1, base + coff[j]);
+                pre[j][2] = ldg(in2, base + coff[j]);
             }
     };
 
-    // compose: the field's planes around the output plane, tile + 1-voxel halo
-    int uoff[NU];
-    float upre[NU][3];
-    if constexpr (COMPOSE) {
-#pragma unroll
-        for (int j = 0; j < NU; ++j) {
-            const int c = tid + j * NT;
-            const int r = c / UW, q = c - r * UW;
-            uoff[j] = clampi(x0 - 1 + q, 0, nx - 1) + nx * clampi(y0 - 1 + r, 0, ny - 1);
-        }
-    }
-    auto u_load = [&](int p) {
-        if constexpr (COMPOSE) {
-            const int base = nxy * clampi(p, 0, nz - 1);
-#pragma unroll
-            for (int j = 0; j < NU; ++j)
-                if (tid + j * NT < UCELLS) {
-                    upre[j][0] = a.u[0][base + uoff[j]];
-                    upre[j][1] = a.u[1][base + uoff[j]];
-                    upre[j][2] = a.u[2][base + uoff[j]];
-                }
-        }
-    };
-    auto u_store = [&](int p) {
-        if constexpr (COMPOSE) {
-            const int sl = (p - z0 + 1) % 3;
-#pragma unroll
-            for (int j = 0; j < NU; ++j) {
-                const int c = tid + j * NT;
-                if (c < UCELLS) {
-                    Us[0][sl][c] = upre[j][0];
-                    Us[1][sl][c] = upre[j][1];
-                    Us[2][sl][c] = upre[j][2];
-                }
-            }
-        }
-    };
-
-    // x then y pass of the plane held in `pre`; `p1` is prefetched meanwhile.  In compose
-    // mode the u plane `ustore` (loaded earlier) goes into its ring slot and u plane
-    // `uload` is loaded.
-    auto filter_plane = [&](int p1, bool more, int ustore, int uload, float out[3]) {
+    // x then y pass of the plane held in `pre`; `p1` is prefetched meanwhile
+    auto filter_plane = [&](int p1, bool more, float out[3]) {
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             const int c = tid + j * NT;
@@ -577,10 +449,6 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
                 for (int m = 1; m <= R; ++m) s = __builtin_fmaf(w[m], raw[k][r][q + R - m] + raw[k][r][q + R + m], s);
                 xs[k][r][q] = s;
             }
-        }
-        if (ustore >= 0) {
-            u_store(ustore);
-            if (uload >= 0) u_load(uload);
         }
         __syncthreads();
 #pragma unroll
@@ -607,31 +475,20 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
     };
 
     float v3[3];
-    if constexpr (COMPOSE) {  // u planes z0 - 1 and z0 into the ring, z0 + 1 into registers
-        u_load(z0 - 1);
-        u_store(z0 - 1);
-        u_load(z0);
-        u_store(z0);
-        u_load(z0 + 1);
-    }
     prefetch(z0 - R);
     for (int q = 0; q < 2 * R; ++q) {
-        filter_plane(z0 - R + q + 1, true, -1, -1, v3);
+        filter_plane(z0 - R + q + 1, true, v3);
         push(v3);
     }
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < nx && gy < ny;
-    // smoothing of u: the warp of I0 with the new u at plane z is issued after the plane's
-    // store and finished after the next plane has been filtered
     WarpPending wp;
     int wv = -1;
     for (int z = z0; z < z1; ++z) {
-        filter_plane(z + R + 1, z + 1 < z1, COMPOSE ? z + 1 : -1, z + 2 <= z1 ? z + 2 : -1, v3);
+        filter_plane(z + R + 1, z + 1 < z1, v3);
         push(v3);
-        if constexpr (!COMPOSE) {
-            if (wv >= 0) warp_finish(a.warp, wp, wv);
-            wv = -1;
-        }
+        if (wv >= 0) warp_finish(a.warp, wp, wv);
+        wv = -1;
         if (own) {
             const int v = gx + nx * gy + nxy * z;
             float s[3];
@@ -641,54 +498,331 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
 #pragma unroll
                 for (int m = 1; m <= R; ++m) t = __builtin_fmaf(w[m], ring[k][R - m] + ring[k][R + m], t);
                 s[k] = t;
+                stg(a.out[k], v, t);
             }
-            if constexpr (COMPOSE) {
-                const Split sx = split_axis(gx, s[0], nx);
-                const Split sy = split_axis(gy, s[1], ny);
-                const Split sz = split_axis(z, s[2], nz);
-                const bool near = sx.i0 >= gx - 1 && sx.i1 <= gx + 1 && sy.i0 >= gy - 1 && sy.i1 <= gy + 1 &&
-                                  sz.i0 >= z - 1 && sz.i1 <= z + 1;
-                if (near) {  // all corners in the staged planes
-                    const int cx0 = sx.i0 - (x0 - 1), cx1 = sx.i1 - (x0 - 1);
-                    const int ry0 = (sy.i0 - (y0 - 1)) * UW, ry1 = (sy.i1 - (y0 - 1)) * UW;
-                    const int sl0 = (sz.i0 - z0 + 1) % 3, sl1 = (sz.i1 - z0 + 1) % 3;
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        float f[8];
-                        f[0] = Us[k][sl0][ry0 + cx0];
-                        f[1] = Us[k][sl0][ry0 + cx1];
-                        f[2] = Us[k][sl0][ry1 + cx0];
-                        f[3] = Us[k][sl0][ry1 + cx1];
-                        f[4] = Us[k][sl1][ry0 + cx0];
-                        f[5] = Us[k][sl1][ry0 + cx1];
-                        f[6] = Us[k][sl1][ry1 + cx0];
-                        f[7] = Us[k][sl1][ry1 + cx1];
-                        a.out[k][v] = s[k] + lerp8(f, sx.t, sy.t, sz.t);
-                    }
-                } else {
-                    const Corners q = corners(sx, sy, sz, nx, nxy);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) a.out[k][v] = s[k] + trilinear(a.u[k], q);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) a.out[k][v] = s[k];
-                warp_issue(a.warp, gx, gy, z, s[0], s[1], s[2], wp);
-                wv = v;
-            }
+            warp_issue(a.warp, gx, gy, z, s[0], s[1], s[2], wp);
+            wv = v;
         }
     }
-    if constexpr (!COMPOSE) {
-        if (wv >= 0) warp_finish(a.warp, wp, wv);
-    }
+    if (wv >= 0) warp_finish(a.warp, wp, wv);
 }
 
-template <int R, int TY, bool COMPOSE>
+template <int R, int TY>
 __global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
 {
     const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
     const int q = pair_of(b.prefix, b.n, L);
-    smooth_tile<R, TY, COMPOSE>(b.d[q], L - b.prefix[q]);
+    smooth_tile<R, TY>(b.d[q], L - b.prefix[q]);
+}
+
+// ============================================================================
+// One iteration up to the composite update, fused: kernels 2 and 3 (gradient and Eq.7) give
+// du, kernel 1 smooths it with the fluid Gaussian (clamped indices), and kernel 4 composes
+// the smoothed step s with the field: u_c(x) = s(x) + u(x + s(x)), u gathered trilinearly.
+//
+// A block owns a 64 x TY column tile and a chunk of z planes.  It marches through the
+// planes z0 - R .. z1 - 1 + R that its z pass needs; for each distinct clamped plane it
+// evaluates du on the tile + R halo (the cells the x and y passes read), straight into LDS,
+// so du never goes to memory.  A halo cell is evaluated at its clamped voxel, which gives
+// the clamped-index smoothing exactly.  The I0~ planes (and structure bits) of the stencils,
+// tile + R + 1 halo, go through a 4-slot LDS ring indexed by plane, prefetched one plane
+// ahead; the field's planes around the output plane (tile + 1 halo) go through a 3-slot
+// ring for the compose gathers, with a global fallback when |s| >= 1.
+// ============================================================================
+template <int R, int TY>
+__device__ __forceinline__ void step_tile(const StepArgs &a, int L)
+{
+    constexpr int WD = kTileX + 2 * R, HT = TY + 2 * R, NT = kTileX * TY;
+    constexpr int CELLS = HT * WD, NP = (CELLS + NT - 1) / NT;
+    constexpr int WW = WD + 2, WH = HT + 2, WCELLS = WW * WH, NW = (WCELLS + NT - 1) / NT;
+    constexpr int UW = kTileX + 2, UH = TY + 2, UCELLS = UW * UH, NU = (UCELLS + NT - 1) / NT;
+    __shared__ float Wr[4][WCELLS];    // I0~ planes, slot = plane & 3
+    __shared__ uint8_t Fr[4][WCELLS];  // their stencil structure bits
+    __shared__ float raw[3][HT][WD];   // du on the tile + R halo
+    __shared__ float xs[3][HT][kTileX];
+    __shared__ float Us[3][3][UCELLS];  // u planes z-1..z+1, slot (p - z0 + 1) % 3
+    __shared__ float dq[TY][kTileX];   // squared metric terms of the tile's voxels
+
+    const int tid = threadIdx.x;
+    const int tx = tid % kTileX, ty = tid / kTileX;
+    const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
+    const TileCoord tc = tile_of(TY, a.tz, a.d, L);
+    const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
+    const bool masked = a.F != nullptr;
+    const bool metric = a.partials != nullptr;
+    float w[R + 1];
+#pragma unroll
+    for (int m = 0; m <= R; ++m) w[m] = a.w[m];
+
+    // ---- I0~ / structure-bit ring (tile + R + 1 halo), clamped in-plane offsets
+    int woff[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        const int c = tid + j * NT;
+        const int r = c / WW, q = c - r * WW;
+        woff[j] = clampi(x0 - R - 1 + q, 0, nx - 1) + nx * clampi(y0 - R - 1 + r, 0, ny - 1);
+    }
+    float pw[NW];
+    uint32_t pf[NW];
+    auto w_load = [&](int p) {  // p in [0, nz)
+        const int base = nxy * p;
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+            if (tid + j * NT < WCELLS) {
+                pw[j] = ldg(a.wI0, base + woff[j]);
+                pf[j] = masked ? ldg(a.F, base + woff[j]) : 0u;
+            }
+    };
+    auto w_store = [&](int p) {
+        const int sl = p & 3;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const int c = tid + j * NT;
+            if (c < WCELLS) {
+                Wr[sl][c] = pw[j];
+                Fr[sl][c] = (uint8_t)pf[j];
+            }
+        }
+    };
+
+    // ---- du cells (tile + R halo): clamped voxel coordinates, target values one plane ahead
+    int cgx[NP], cgy[NP], dqi[NP];
+    uint32_t inside = 0;  // bit j: cell j is a voxel of the tile inside the volume
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int c = tid + j * NT;
+        const int r = c / WD, q = c - r * WD;
+        cgx[j] = clampi(x0 - R + q, 0, nx - 1);
+        cgy[j] = clampi(y0 - R + r, 0, ny - 1);
+        const bool tile = c < CELLS && r >= R && r < R + TY && q >= R && q < R + kTileX;
+        dqi[j] = tile ? (r - R) * kTileX + (q - R) : -1;
+        if (tile && x0 + q - R < nx && y0 + r - R < ny) inside |= 1u << j;
+    }
+    float pt[NP];
+    uint32_t ptb[NP], pur[NP];
+    auto t_load = [&](int p) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+            if (tid + j * NT < CELLS) {
+                const int v = cgx[j] + nx * cgy[j] + nxy * p;
+                pt[j] = ldg(a.T0, v);
+                ptb[j] = masked ? ldg(a.tbits, v) : 0u;
+                pur[j] = (metric && ((inside >> j) & 1u)) ? ldg(a.uroi, v) : 0u;
+            }
+    };
+
+    // ---- u ring (tile + 1 halo) for the compose gathers
+    int uoff[NU];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+        const int c = tid + j * NT;
+        const int r = c / UW, q = c - r * UW;
+        uoff[j] = clampi(x0 - 1 + q, 0, nx - 1) + nx * clampi(y0 - 1 + r, 0, ny - 1);
+    }
+    float upre[NU][3];
+    auto u_load = [&](int p) {
+        const int base = nxy * clampi(p, 0, nz - 1);
+#pragma unroll
+        for (int j = 0; j < NU; ++j)
+            if (tid + j * NT < UCELLS) {
+                upre[j][0] = ldg(a.u[0], base + uoff[j]);
+                upre[j][1] = ldg(a.u[1], base + uoff[j]);
+                upre[j][2] = ldg(a.u[2], base + uoff[j]);
+            }
+    };
+    auto u_store = [&](int p) {
+        const int sl = (p - z0 + 1) % 3;
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const int c = tid + j * NT;
+            if (c < UCELLS) {
+                Us[0][sl][c] = upre[j][0];
+                Us[1][sl][c] = upre[j][1];
+                Us[2][sl][c] = upre[j][2];
+            }
+        }
+    };
+
+    float ring[3][2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int m = 0; m <= 2 * R; ++m) ring[k][m] = 0.f;
+    auto push = [&](const float v3[3]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int m = 0; m < 2 * R; ++m) ring[k][m] = ring[k][m + 1];
+            ring[k][2 * R] = v3[k];
+        }
+    };
+
+    // planes pa - 1 .. pa + 1 staged, pa + 2 in registers; plane q + 2 is staged while
+    // plane q's du is evaluated, into the slot of plane q - 2
+    const int zs = z0 - R, ze = z1 - 1 + R;
+    const int pa = max(zs, 0), pb = min(ze, nz - 1);
+    w_load(max(pa - 1, 0));
+    w_store(max(pa - 1, 0));
+    w_load(pa);
+    w_store(pa);
+    w_load(min(pa + 1, nz - 1));
+    w_store(min(pa + 1, nz - 1));
+    if (pa + 1 <= pb) w_load(min(pa + 2, nz - 1));
+    t_load(pa);
+    u_load(z0 - 1);
+    u_store(z0 - 1);
+    u_load(z0);
+    u_store(z0);
+    u_load(z0 + 1);
+
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own = gx < nx && gy < ny;
+    const int ntx = (nx + kTileX - 1) / kTileX;
+    float last[3] = {0.f, 0.f, 0.f};
+    int prev = -1;
+    __syncthreads();
+    for (int l = zs; l <= ze; ++l) {
+        const int pc = clampi(l, 0, nz - 1);
+        const int z = l - R;         // output plane once the ring is full
+        const bool out = l >= z0 + R;
+        float v3[3];
+        if (pc != prev) {
+            // ---- du on plane pc, tile + R halo
+            const int s0 = pc & 3, sm = max(pc - 1, 0) & 3, sp = min(pc + 1, nz - 1) & 3;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const int c = tid + j * NT;
+                if (c < CELLS) {
+                    const int cx = cgx[j], cy = cgy[j];
+                    const int wo = (cy - (y0 - R - 1)) * WW + (cx - (x0 - R - 1));
+                    float w7[7];
+                    uint32_t f7[7];
+                    w7[0] = Wr[s0][wo];
+                    w7[1] = Wr[s0][wo - 1];
+                    w7[2] = Wr[s0][wo + 1];
+                    w7[3] = Wr[s0][wo - WW];
+                    w7[4] = Wr[s0][wo + WW];
+                    w7[5] = Wr[sm][wo];
+                    w7[6] = Wr[sp][wo];
+                    if (masked) {
+                        f7[0] = Fr[s0][wo];
+                        f7[1] = Fr[s0][wo - 1];
+                        f7[2] = Fr[s0][wo + 1];
+                        f7[3] = Fr[s0][wo - WW];
+                        f7[4] = Fr[s0][wo + WW];
+                        f7[5] = Fr[sm][wo];
+                        f7[6] = Fr[sp][wo];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 7; ++q) f7[q] = 0u;
+                    }
+                    float du[3], d;
+                    force_at(a, w7, f7, pt[j], ptb[j], cx, cy, pc, du, &d);
+                    const int r = c / WD, q = c - r * WD;
+                    raw[0][r][q] = du[0];
+                    raw[1][r][q] = du[1];
+                    raw[2][r][q] = du[2];
+                    if (metric && dqi[j] >= 0) {
+                        const float e = d * a.inv_norm;
+                        (&dq[0][0])[dqi[j]] = pur[j] ? e * e : 0.f;
+                    }
+                }
+            }
+            if (pc + 1 <= pb) {
+                if (pc + 2 <= nz - 1) w_store(pc + 2);
+                if (pc + 2 <= pb) w_load(min(pc + 3, nz - 1));
+                t_load(pc + 1);
+            }
+            __syncthreads();
+            for (int c = tid; c < HT * kTileX; c += NT) {
+                const int r = c / kTileX, q = c - r * kTileX;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float s = w[0] * raw[k][r][q + R];
+#pragma unroll
+                    for (int m = 1; m <= R; ++m)
+                        s = __builtin_fmaf(w[m], raw[k][r][q + R - m] + raw[k][r][q + R + m], s);
+                    xs[k][r][q] = s;
+                }
+            }
+            // stopping metric: one partial per 64-voxel row segment (a wave is one tile
+            // row), a grouping that does not depend on the launch geometry
+            if (metric && pc >= z0 && pc < z1 && gy < ny) {
+                const float rs = wave_sum(dq[ty][tx]);
+                if (tx == 0) stg(a.partials, (pc * ny + gy) * ntx + x0 / kTileX, rs);
+            }
+            if (out) {
+                u_store(z + 1);
+                if (z + 2 <= z1) u_load(z + 2);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                float s = w[0] * xs[k][ty + R][tx];
+#pragma unroll
+                for (int m = 1; m <= R; ++m) s = __builtin_fmaf(w[m], xs[k][ty + R - m][tx] + xs[k][ty + R + m][tx], s);
+                v3[k] = s;
+                last[k] = s;
+            }
+            prev = pc;
+        } else {  // a clamped plane again (past a volume end): same xy-smoothed values
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v3[k] = last[k];
+            if (out) {
+                __syncthreads();
+                u_store(z + 1);
+                if (z + 2 <= z1) u_load(z + 2);
+                __syncthreads();
+            }
+        }
+        push(v3);
+        if (out && own) {
+            const int v = gx + nx * gy + nxy * z;
+            float s[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                float t = w[0] * ring[k][R];
+#pragma unroll
+                for (int m = 1; m <= R; ++m) t = __builtin_fmaf(w[m], ring[k][R - m] + ring[k][R + m], t);
+                s[k] = t;
+            }
+            const Split sx = split_axis(gx, s[0], nx);
+            const Split sy = split_axis(gy, s[1], ny);
+            const Split sz = split_axis(z, s[2], nz);
+            const bool near = sx.i0 >= gx - 1 && sx.i1 <= gx + 1 && sy.i0 >= gy - 1 && sy.i1 <= gy + 1 &&
+                              sz.i0 >= z - 1 && sz.i1 <= z + 1;
+            if (near) {  // all corners in the staged planes
+                const int cx0 = sx.i0 - (x0 - 1), cx1 = sx.i1 - (x0 - 1);
+                const int ry0 = (sy.i0 - (y0 - 1)) * UW, ry1 = (sy.i1 - (y0 - 1)) * UW;
+                const int sl0 = (sz.i0 - z0 + 1) % 3, sl1 = (sz.i1 - z0 + 1) % 3;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float f[8];
+                    f[0] = Us[k][sl0][ry0 + cx0];
+                    f[1] = Us[k][sl0][ry0 + cx1];
+                    f[2] = Us[k][sl0][ry1 + cx0];
+                    f[3] = Us[k][sl0][ry1 + cx1];
+                    f[4] = Us[k][sl1][ry0 + cx0];
+                    f[5] = Us[k][sl1][ry0 + cx1];
+                    f[6] = Us[k][sl1][ry1 + cx0];
+                    f[7] = Us[k][sl1][ry1 + cx1];
+                    stg(a.uc[k], v, s[k] + lerp8(f, sx.t, sy.t, sz.t));
+                }
+            } else {
+                const Corners q = corners(sx, sy, sz, nx, nxy);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) stg(a.uc[k], v, s[k] + trilinear(a.u[k], q));
+            }
+        }
+    }
+}
+
+template <int R, int TY>
+__global__ void __launch_bounds__(kTileX *TY) k_step_batch(StepBatch b)
+{
+    const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
+    const int q = pair_of(b.prefix, b.n, L);
+    step_tile<R, TY>(b.d[q], L - b.prefix[q]);
 }
 
 // Warp of the moving image with the field at the start of a level (the smoothing of u
@@ -978,56 +1112,59 @@ static int tiles_xy(Dims d, int ty) { return ((d.nx + kTileX - 1) / kTileX) * ((
 
 int tile_blocks(Dims d, int ty, int tz) { return tiles_xy(d, ty) * ((d.nz + tz - 1) / tz); }
 
+// one launch per (radius, tile rows) instantiation
 template <int TY>
-static hipError_t force_batch_ty(const ForceBatch &b, hipStream_t s)
+static hipError_t step_batch_ty(const StepBatch &b, int radius, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_force_batch<TY>), dim3(b.prefix[b.n]), dim3(kTileX * TY), 0, s, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_force_batch(const ForceBatch &b, int ty, hipStream_t s)
-{
-    if (b.n < 1 || b.n > kBatchForce || b.prefix[b.n] < 1) return hipErrorInvalidValue;
-    switch (ty) {
-    case 4: return force_batch_ty<4>(b, s);
-    case 8: return force_batch_ty<8>(b, s);
-    case 16: return force_batch_ty<16>(b, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int R, int TY>
-static hipError_t smooth_batch_r_ty(const SmoothBatch &b, bool compose, hipStream_t s)
-{
-    if (compose)
-        hipLaunchKernelGGL((k_smooth_batch<R, TY, true>), dim3(b.prefix[b.n]), dim3(kTileX * TY), 0, s, b);
-    else
-        hipLaunchKernelGGL((k_smooth_batch<R, TY, false>), dim3(b.prefix[b.n]), dim3(kTileX * TY), 0, s, b);
-    return hipGetLastError();
-}
-
-template <int TY>
-static hipError_t smooth_batch_ty(const SmoothBatch &b, int radius, bool compose, hipStream_t s)
-{
+    const dim3 grid(b.prefix[b.n]), block(kTileX * TY);
     switch (radius) {
-    case 0: return smooth_batch_r_ty<0, TY>(b, compose, s);
-    case 1: return smooth_batch_r_ty<1, TY>(b, compose, s);
-    case 2: return smooth_batch_r_ty<2, TY>(b, compose, s);
-    case 3: return smooth_batch_r_ty<3, TY>(b, compose, s);
-    case 4: return smooth_batch_r_ty<4, TY>(b, compose, s);
-    case 5: return smooth_batch_r_ty<5, TY>(b, compose, s);
-    case 6: return smooth_batch_r_ty<6, TY>(b, compose, s);
+    case 0: hipLaunchKernelGGL((k_step_batch<0, TY>), grid, block, 0, s, b); break;
+    case 1: hipLaunchKernelGGL((k_step_batch<1, TY>), grid, block, 0, s, b); break;
+    case 2: hipLaunchKernelGGL((k_step_batch<2, TY>), grid, block, 0, s, b); break;
+    case 3: hipLaunchKernelGGL((k_step_batch<3, TY>), grid, block, 0, s, b); break;
+    case 4: hipLaunchKernelGGL((k_step_batch<4, TY>), grid, block, 0, s, b); break;
+    case 5: hipLaunchKernelGGL((k_step_batch<5, TY>), grid, block, 0, s, b); break;
+    case 6: hipLaunchKernelGGL((k_step_batch<6, TY>), grid, block, 0, s, b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batch(const StepBatch &b, int radius, int ty, hipStream_t s)
+{
+    if (b.n < 1 || b.n > kBatchStep || b.prefix[b.n] < 1) return hipErrorInvalidValue;
+    switch (ty) {
+    case 4: return step_batch_ty<4>(b, radius, s);
+    case 8: return step_batch_ty<8>(b, radius, s);
+    case 16: return step_batch_ty<16>(b, radius, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, bool compose, int ty, hipStream_t s)
+template <int TY>
+static hipError_t smooth_batch_ty(const SmoothBatch &b, int radius, hipStream_t s)
+{
+    const dim3 grid(b.prefix[b.n]), block(kTileX * TY);
+    switch (radius) {
+    case 0: hipLaunchKernelGGL((k_smooth_batch<0, TY>), grid, block, 0, s, b); break;
+    case 1: hipLaunchKernelGGL((k_smooth_batch<1, TY>), grid, block, 0, s, b); break;
+    case 2: hipLaunchKernelGGL((k_smooth_batch<2, TY>), grid, block, 0, s, b); break;
+    case 3: hipLaunchKernelGGL((k_smooth_batch<3, TY>), grid, block, 0, s, b); break;
+    case 4: hipLaunchKernelGGL((k_smooth_batch<4, TY>), grid, block, 0, s, b); break;
+    case 5: hipLaunchKernelGGL((k_smooth_batch<5, TY>), grid, block, 0, s, b); break;
+    case 6: hipLaunchKernelGGL((k_smooth_batch<6, TY>), grid, block, 0, s, b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, int ty, hipStream_t s)
 {
     if (b.n < 1 || b.n > kBatchSmooth || b.prefix[b.n] < 1) return hipErrorInvalidValue;
     switch (ty) {
-    case 4: return smooth_batch_ty<4>(b, radius, compose, s);
-    case 8: return smooth_batch_ty<8>(b, radius, compose, s);
-    case 16: return smooth_batch_ty<16>(b, radius, compose, s);
+    case 4: return smooth_batch_ty<4>(b, radius, s);
+    case 8: return smooth_batch_ty<8>(b, radius, s);
+    case 16: return smooth_batch_ty<16>(b, radius, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -139,11 +139,11 @@ Dims level_dims(Dims d0, int l)
 
 // launch geometry (tile rows, z planes per block) of the iteration kernels
 struct Tuning {
-    int force_ty = 4, force_tz = 8;
+    int step_ty = 8, step_tz = 32;
     int smooth_ty = 8, smooth_tz = 32;
 };
 
-// CGDIR_TUNE="force_ty,force_tz,smooth_ty,smooth_tz" overrides the launch geometry
+// CGDIR_TUNE="step_ty,step_tz,smooth_ty,smooth_tz" overrides the launch geometry
 Tuning tuning_from_env()
 {
     Tuning t;
@@ -164,7 +164,7 @@ size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, 
 {
     const size_t n0 = (size_t)d0.n();
     size_t b = 0;
-    b += 3 * align_up(3 * n0 * sizeof(float));  // u, du, uc
+    b += 2 * align_up(3 * n0 * sizeof(float));  // u, u_c
     b += align_up(n0 * sizeof(float));          // warped moving image
     for (int l = 1; l < p.levels; ++l) b += 2 * align_up((size_t)level_dims(d0, l).n() * sizeof(float));
     if (host_images) b += 2 * align_up(n0 * sizeof(float));
@@ -183,10 +183,9 @@ size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, 
 
 // ------------------------------------------------------------------ profiling
 
-enum KernelId { K_FORCE, K_SMOOTH_COMPOSE, K_SMOOTH, K_DELTA, K_RESTRICT, K_PROLONG, K_PACK, K_UROI,
-                K_WARP, K_MISC, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"force", "smooth_compose", "smooth", "delta", "restrict",
-                                     "prolong", "pack_masks", "uroi", "warp", "misc"};
+enum KernelId { K_STEP, K_SMOOTH, K_DELTA, K_RESTRICT, K_PROLONG, K_PACK, K_UROI, K_WARP, K_MISC, K_COUNT };
+const char *kKernelNames[K_COUNT] = {"step", "smooth", "delta", "restrict", "prolong",
+                                     "pack_masks", "uroi", "warp", "misc"};
 
 // ------------------------------------------------------------------ tile autotuner
 // A pair's results do not depend on the tile shape of any kernel, so the first launches of
@@ -196,24 +195,24 @@ const char *kKernelNames[K_COUNT] = {"force", "smooth_compose", "smooth", "delta
 struct TileCfg {
     int ty, tz;
 };
-const TileCfg kForceCands[] = {{4, 16}, {4, 4}, {4, 8}, {4, 32}, {8, 16}, {8, 32}, {8, 128}, {16, 16}, {16, 128}};
+const TileCfg kStepCands[] = {{8, 32}, {8, 16}, {8, 64}, {8, 128}, {16, 16}, {16, 32}, {16, 64}, {16, 128}, {4, 32}, {4, 128}, {8, 8}, {4, 8}, {4, 16}};
 const TileCfg kSmoothCands[] = {{8, 32}, {8, 8}, {8, 16}, {8, 64}, {8, 128}, {16, 16}, {16, 32}, {16, 64},
                                 {16, 128}, {4, 16}, {4, 64}};
 
 class Tuner {
   public:
     bool enabled = true;
-    TileCfg fixed_force{4, 8}, fixed_smooth{8, 32};
+    TileCfg fixed_step{8, 32}, fixed_smooth{8, 32};
     bool log = false;
 
     // shape to use for the next launch of group `key`; *measure >= 0 asks the caller to time
     // the launch with events ev[0], ev[1] and hand them back through record()
-    TileCfg choose(bool force, const std::string &key, int *measure)
+    TileCfg choose(bool step, const std::string &key, int *measure)
     {
         *measure = -1;
-        const TileCfg *c = force ? kForceCands : kSmoothCands;
-        const int nc = force ? (int)(sizeof(kForceCands) / sizeof(TileCfg)) : (int)(sizeof(kSmoothCands) / sizeof(TileCfg));
-        if (!enabled) return force ? fixed_force : fixed_smooth;
+        const TileCfg *c = step ? kStepCands : kSmoothCands;
+        const int nc = step ? (int)(sizeof(kStepCands) / sizeof(TileCfg)) : (int)(sizeof(kSmoothCands) / sizeof(TileCfg));
+        if (!enabled) return step ? fixed_step : fixed_smooth;
         Entry &e = table_[key];
         if (e.ms.empty()) e.ms.assign(nc, -1.f);
         if (e.best >= 0) return c[e.best];
@@ -238,9 +237,8 @@ class Tuner {
         }
         return c[0];
     }
-    void record(bool force, const std::string &key, int cand, hipEvent_t a, hipEvent_t b)
+    void record(const std::string &key, int cand, hipEvent_t a, hipEvent_t b)
     {
-        (void)force;
         table_[key].pending.push_back({cand, a, b});
     }
     hipEvent_t event()
@@ -492,7 +490,7 @@ struct Job {
     std::vector<void *> allocs;
     const float *I0[CGDIR_MAX_LEVELS] = {}, *T0[CGDIR_MAX_LEVELS] = {};
     uint8_t *mbits = nullptr, *tbits = nullptr, *uroi = nullptr, *mocc = nullptr;
-    float *ubuf = nullptr, *dubuf = nullptr, *ucbuf = nullptr;
+    float *ubuf = nullptr, *ucbuf = nullptr;
     float *wI0 = nullptr, *Kbuf = nullptr;
     uint8_t *Fbuf = nullptr;
     float *partials = nullptr;
@@ -561,10 +559,9 @@ struct Job {
     {
         const size_t n0 = (size_t)d0.n();
         ubuf = (float *)take(3 * n0 * sizeof(float));
-        dubuf = (float *)take(3 * n0 * sizeof(float));
         ucbuf = (float *)take(3 * n0 * sizeof(float));
         wI0 = (float *)take(n0 * sizeof(float));
-        bool ok = ubuf && dubuf && ucbuf && wI0;
+        bool ok = ubuf && ucbuf && wI0;
         if (host_images) {
             float *a = (float *)take(n0 * sizeof(float));
             float *b = (float *)take(n0 * sizeof(float));
@@ -642,7 +639,8 @@ struct Job {
             }
             HIP_TRY(timed(ctx, K_PACK * 8 + 7, (double)n0, [&] { return launch_brick_occupancy(mbits, d0, mocc, s); }));
         }
-        uint8_t *rowdist = (uint8_t *)dubuf;  // scratch during setup
+        // the u_c buffer (12 bytes per voxel) is scratch until the first iteration
+        uint8_t *rowdist = (uint8_t *)ucbuf + n0;
         if (delta_on) {
             if (k > 0) {
                 HIP_TRY(timed(ctx, K_UROI * 8 + 7, (double)n0,
@@ -656,7 +654,7 @@ struct Job {
         bool need_auto = false;
         for (int i = 0; i < k; ++i) need_auto |= sign[i] == 0;
         if (need_auto) {
-            uint8_t *dil = (uint8_t *)ucbuf;
+            uint8_t *dil = (uint8_t *)ucbuf;  // rowdist follows it
             double *parts = sign_parts;
             for (int i = 0; i < k; ++i) {
                 if (sign[i] != 0) continue;
@@ -677,8 +675,8 @@ struct Job {
             dx.nx = (din.nx + 1) / 2;
             Dims dy = dx;
             dy.ny = (dx.ny + 1) / 2;
-            float *t1 = dubuf;                   // <= n0 floats
-            float *t2 = dubuf + (size_t)n0;      // <= n0 floats
+            float *t1 = ucbuf;                   // <= n0 floats
+            float *t2 = ucbuf + (size_t)n0;      // <= n0 floats
             for (int img = 0; img < 2; ++img) {
                 const float *src = img == 0 ? I0[l - 1] : T0[l - 1];
                 float *dst = (float *)(img == 0 ? I0[l] : T0[l]);
@@ -733,10 +731,10 @@ struct Job {
         if (level < L - 1) {
             const Dims dc = level_dims(d0, level + 1);
             const float *uc[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
-            float *uf[3] = {comp(dubuf, 0), comp(dubuf, 1), comp(dubuf, 2)};
+            float *uf[3] = {comp(ucbuf, 0), comp(ucbuf, 1), comp(ucbuf, 2)};
             HIP_TRY(timed(ctx, K_PROLONG * 8 + level, (double)df.n(),
                           [&] { return launch_prolong(uc, dc, uf, df, ctx->stream); }));
-            std::swap(ubuf, dubuf);
+            std::swap(ubuf, ucbuf);
         }
         const float *u3[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
         const WarpArgs w = warp_args();
@@ -747,36 +745,38 @@ struct Job {
     // ---- one iteration of the loop at the current level, as batched-launch descriptors
     bool metric() const { return delta_on && level == 0; }
 
-    ForceArgs force_args() const
+    // force, fluid smoothing, compose: u -> u_c
+    StepArgs step_args() const
     {
         const Dims d = level_dims(d0, level);
         const bool contour = contour_at(level);
-        ForceArgs fa{};
-        fa.wI0 = wI0;
-        fa.F = contour ? Fbuf : nullptr;
-        fa.K = contour ? Kbuf : nullptr;
-        fa.T0 = T0[level];
-        fa.tbits = contour ? tbits : nullptr;
-        fa.uroi = metric() ? uroi : nullptr;
-        fa.I0 = I0[level];
-        fa.mbits = contour ? mbits : nullptr;
+        StepArgs sa{};
+        sa.wI0 = wI0;
+        sa.F = contour ? Fbuf : nullptr;
+        sa.K = contour ? Kbuf : nullptr;
+        sa.T0 = T0[level];
+        sa.tbits = contour ? tbits : nullptr;
+        sa.uroi = metric() ? uroi : nullptr;
+        sa.I0 = I0[level];
+        sa.mbits = contour ? mbits : nullptr;
         for (int c = 0; c < 3; ++c) {
-            fa.u[c] = comp(ubuf, c);
-            fa.du[c] = comp(dubuf, c);
+            sa.u[c] = comp(ubuf, c);
+            sa.uc[c] = comp(ucbuf, c);
         }
-        fa.partials = metric() ? partials : nullptr;
-        fa.d = d;
-        fa.k = contour ? k : 0;
-        fa.lam_sum = 0.f;
+        sa.partials = metric() ? partials : nullptr;
+        sa.d = d;
+        sa.k = contour ? k : 0;
+        sa.lam_sum = 0.f;
         for (int i = 0; i < kMaxStructs; ++i) {
-            fa.lam[i] = i < k ? lam[i] : 0.f;
-            fa.hs[i] = i < k ? hs[i] : 0.f;
-            if (i < fa.k) fa.lam_sum += fa.lam[i];
+            sa.lam[i] = i < k ? lam[i] : 0.f;
+            sa.hs[i] = i < k ? hs[i] : 0.f;
+            if (i < sa.k) sa.lam_sum += sa.lam[i];
         }
-        fa.c0 = req.params.intensity_offset;
-        fa.inv_norm = 1.0f / req.params.norm_range;
-        fa.tz = ctx->tune.force_tz;
-        return fa;
+        sa.c0 = req.params.intensity_offset;
+        sa.inv_norm = 1.0f / req.params.norm_range;
+        for (int m = 0; m <= kMaxRadius; ++m) sa.w[m] = wf[m];
+        sa.tz = ctx->tune.step_tz;
+        return sa;
     }
 
     DeltaJob delta_job() const
@@ -789,28 +789,12 @@ struct Job {
         return j;
     }
 
-    // smooth du, compose with u -> u_c
-    SmoothArgs compose_args() const
-    {
-        SmoothArgs sa{};
-        for (int c = 0; c < 3; ++c) {
-            sa.in[c] = comp(dubuf, c);
-            sa.u[c] = comp(ubuf, c);
-            sa.out[c] = comp(ucbuf, c);
-        }
-        sa.d = level_dims(d0, level);
-        sa.tz = ctx->tune.smooth_tz;
-        for (int m = 0; m <= kMaxRadius; ++m) sa.w[m] = wf[m];
-        return sa;
-    }
-
     // smooth u_c -> u
     SmoothArgs smooth_args() const
     {
         SmoothArgs sb{};
         for (int c = 0; c < 3; ++c) {
             sb.in[c] = comp(ucbuf, c);
-            sb.u[c] = nullptr;
             sb.out[c] = comp(ubuf, c);
         }
         sb.d = level_dims(d0, level);
@@ -901,9 +885,9 @@ struct Job {
 };
 
 // ------------------------------------------------------------------ one tick
-// One iteration of every job that has work left, as batched launches: each phase (force,
-// metric, smooth+compose, smooth) is one launch over the tiles of up to kBatchForce /
-// kBatchSmooth jobs (the smoothing launches are grouped by Gaussian radius).  A job that
+// One iteration of every job that has work left, as batched launches: each phase (step,
+// metric, smooth) is one launch over the tiles of up to kBatchStep / kBatchSmooth jobs,
+// grouped by the radius of the phase's Gaussian.  A job that
 // fails stops with its code in `codes`; the others go on.
 namespace cgdir {
 namespace {
@@ -921,7 +905,6 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
     int lvl = jobs[act[0]]->level;  // profiling slot: the common level, 6 when mixed
     for (int i : act)
         if (jobs[i]->level != lvl) lvl = 6;
-    const Tuning &t = c->tune;
 
     auto shapes_key = [&](char kind, int radius, const int *idx, int n) {
         std::string key(1, kind);
@@ -933,33 +916,41 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
         return key;
     };
     // a launch, timed for the tuner when it asks
-    auto tuned = [&](bool measure_it, bool force, const std::string &key, int cand, auto &&fn) -> hipError_t {
+    auto tuned = [&](bool measure_it, const std::string &key, int cand, auto &&fn) -> hipError_t {
         if (!measure_it) return fn();
         hipEvent_t ea = c->tuner.event(), eb = c->tuner.event();
         if (!ea || !eb) return fn();
         hipEventRecord(ea, s);
         const hipError_t e = fn();
         hipEventRecord(eb, s);
-        c->tuner.record(force, key, cand, ea, eb);
+        c->tuner.record(key, cand, ea, eb);
         return e;
     };
 
-    for (size_t b = 0; b < act.size(); b += kBatchForce) {
-        ForceBatch fb{};
-        fb.n = (int)std::min<size_t>(kBatchForce, act.size() - b);
-        const std::string key = shapes_key('F', 0, &act[b], fb.n);
-        int cand = -1;
-        const TileCfg cfg = c->tuner.choose(true, key, &cand);
-        double vox = 0.0;
-        for (int q = 0; q < fb.n; ++q) {
-            fb.d[q] = jobs[act[b + q]]->force_args();
-            fb.d[q].tz = cfg.tz;
-            fb.prefix[q + 1] = fb.prefix[q] + tile_blocks(fb.d[q].d, cfg.ty, cfg.tz);
-            vox += (double)fb.d[q].d.n();
+    std::map<int, std::vector<int>> by_rf, by_rd;
+    for (int i : act) {
+        by_rf[jobs[i]->Rf].push_back(i);
+        by_rd[jobs[i]->Rd].push_back(i);
+    }
+    for (auto &g : by_rf) {
+        const std::vector<int> &v = g.second;
+        for (size_t b = 0; b < v.size(); b += kBatchStep) {
+            StepBatch sb{};
+            sb.n = (int)std::min<size_t>(kBatchStep, v.size() - b);
+            const std::string key = shapes_key('U', g.first, &v[b], sb.n);
+            int cand = -1;
+            const TileCfg cfg = c->tuner.choose(true, key, &cand);
+            double vox = 0.0;
+            for (int q = 0; q < sb.n; ++q) {
+                sb.d[q] = jobs[v[b + q]]->step_args();
+                sb.d[q].tz = cfg.tz;
+                sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, cfg.ty, cfg.tz);
+                vox += (double)sb.d[q].d.n();
+            }
+            HIP_TRY(timed(c, K_STEP * 8 + lvl, vox, [&] {
+                return tuned(cand >= 0, key, cand, [&] { return launch_step_batch(sb, g.first, cfg.ty, s); });
+            }));
         }
-        HIP_TRY(timed(c, K_FORCE * 8 + lvl, vox, [&] {
-            return tuned(cand >= 0, true, key, cand, [&] { return launch_force_batch(fb, cfg.ty, s); });
-        }));
     }
     {
         DeltaBatch db{};
@@ -971,31 +962,24 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
             }
         }
     }
-    for (int phase = 0; phase < 2; ++phase) {
-        const bool compose = phase == 0;
-        std::map<int, std::vector<int>> by_radius;
-        for (int i : act) by_radius[compose ? jobs[i]->Rf : jobs[i]->Rd].push_back(i);
-        for (auto &g : by_radius) {
-            const std::vector<int> &v = g.second;
-            for (size_t b = 0; b < v.size(); b += kBatchSmooth) {
-                SmoothBatch sb{};
-                sb.n = (int)std::min<size_t>(kBatchSmooth, v.size() - b);
-                const std::string key = shapes_key(compose ? 'C' : 'S', g.first, &v[b], sb.n);
-                int cand = -1;
-                const TileCfg cfg = c->tuner.choose(false, key, &cand);
-                double vox = 0.0;
-                for (int q = 0; q < sb.n; ++q) {
-                    sb.d[q] = compose ? jobs[v[b + q]]->compose_args() : jobs[v[b + q]]->smooth_args();
-                    sb.d[q].tz = cfg.tz;
-                    sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, cfg.ty, cfg.tz);
-                    vox += (double)sb.d[q].d.n();
-                }
-                const int id = compose ? K_SMOOTH_COMPOSE : K_SMOOTH;
-                HIP_TRY(timed(c, id * 8 + lvl, vox, [&] {
-                    return tuned(cand >= 0, false, key, cand,
-                                 [&] { return launch_smooth_batch(sb, g.first, compose, cfg.ty, s); });
-                }));
+    for (auto &g : by_rd) {
+        const std::vector<int> &v = g.second;
+        for (size_t b = 0; b < v.size(); b += kBatchSmooth) {
+            SmoothBatch sb{};
+            sb.n = (int)std::min<size_t>(kBatchSmooth, v.size() - b);
+            const std::string key = shapes_key('S', g.first, &v[b], sb.n);
+            int cand = -1;
+            const TileCfg cfg = c->tuner.choose(false, key, &cand);
+            double vox = 0.0;
+            for (int q = 0; q < sb.n; ++q) {
+                sb.d[q] = jobs[v[b + q]]->smooth_args();
+                sb.d[q].tz = cfg.tz;
+                sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, cfg.ty, cfg.tz);
+                vox += (double)sb.d[q].d.n();
             }
+            HIP_TRY(timed(c, K_SMOOTH * 8 + lvl, vox, [&] {
+                return tuned(cand >= 0, key, cand, [&] { return launch_smooth_batch(sb, g.first, cfg.ty, s); });
+            }));
         }
     }
     for (int i : act) codes[i] = jobs[i]->after_iteration();
@@ -1225,7 +1209,7 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
     c->profile = (desc->flags & CGDIR_CTX_PROFILE) != 0;
     c->tune = tuning_from_env();
     c->tuner.enabled = std::getenv("CGDIR_TUNE") == nullptr;
-    c->tuner.fixed_force = TileCfg{c->tune.force_ty, c->tune.force_tz};
+    c->tuner.fixed_step = TileCfg{c->tune.step_ty, c->tune.step_tz};
     c->tuner.fixed_smooth = TileCfg{c->tune.smooth_ty, c->tune.smooth_tz};
     c->tuner.log = std::getenv("CGDIR_TUNE_LOG") != nullptr;
     if (desc->stream) {

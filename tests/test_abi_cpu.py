@@ -40,9 +40,9 @@ def test_footprint():
     p = cgdir.make_params(levels=3, iters=(150, 150, 150))
     n = 512 * 512 * 128
     fp = cgdir.footprint(512, 512, 128, 8, p)
-    # u, du, u_c (36 B/voxel), warped image (4 B), bit-planes (2 B), stencil structure
+    # u and u_c (24 B/voxel), warped image (4 B), bit-planes (2 B), stencil structure
     # bits and K_i~ (5 B), coarse images (8 B x (1/8 + 1/64))
-    assert 47 * n <= fp <= 49 * n
+    assert 35 * n <= fp <= 37 * n
     assert cgdir.footprint(512, 512, 128, 0, p) < fp
     assert cgdir.footprint(0, 5, 5, 1, p) == 0
     assert cgdir.footprint(5, 5, 5, 9, p) == 0

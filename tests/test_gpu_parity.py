@@ -257,9 +257,11 @@ def test_invalid_arguments(ctx):
     with pytest.raises(cgdir.CgdirError) as e:
         ctx.register(t, m, tm, mm, cgdir.params_for_pair(pair, contour_level_mask=2))
     assert e.value.code == cgdir.E_UNIMPL
-    big = torch.zeros((200, 1024, 1024), dtype=torch.float32, device="cuda")
+    big = torch.zeros((256, 1024, 1024), dtype=torch.float32, device="cuda")
+    one = cgdir.make_params(levels=1, iters=(1,))
+    assert cgdir.footprint(1024, 1024, 256, 0, one) > (6 << 30)   # more than the context's pool
     with pytest.raises(cgdir.CgdirError) as e:
-        ctx.register(big, big, None, None, cgdir.make_params(levels=1, iters=(1,)))
+        ctx.register(big, big, None, None, one)
     assert e.value.code == cgdir.E_NOMEM
 
 

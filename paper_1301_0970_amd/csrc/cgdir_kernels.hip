@@ -41,20 +41,15 @@ struct Split {
 __device__ __forceinline__ Split split_axis(int i, float u, int n)
 {
     const float fu = floorf(u);
-    float t = u - fu;
     const float pb = (float)i + fu;
+    const float top = (float)(n - 1);
+    // below 0 or at/after the last voxel: the border voxel with weight 0; NaN keeps an
+    // in-bounds index (max/min return the non-NaN operand) and a NaN weight.  Branch free.
+    const bool outside = pb < 0.f || pb >= top;
     Split s;
-    if (pb < 0.f) {
-        s.i0 = 0;
-        t = 0.f;
-    } else if (pb >= (float)(n - 1)) {
-        s.i0 = n - 1;
-        t = 0.f;
-    } else {
-        s.i0 = (pb == pb) ? (int)pb : 0;  // NaN keeps an in-bounds index and a NaN weight
-    }
+    s.i0 = (int)fminf(fmaxf(pb, 0.f), top);
     s.i1 = min(s.i0 + 1, n - 1);
-    s.t = t;
+    s.t = outside ? 0.f : u - fu;
     return s;
 }
 
@@ -667,7 +662,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     w_store(pa);
     w_load(min(pa + 1, nz - 1));
     w_store(min(pa + 1, nz - 1));
-    if (pa + 1 <= pb) w_load(min(pa + 2, nz - 1));
+    w_load(min(pa + 2, nz - 1));
     t_load(pa);
     u_load(z0 - 1);
     u_store(z0 - 1);
@@ -728,11 +723,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                     }
                 }
             }
-            if (pc + 1 <= pb) {
-                if (pc + 2 <= nz - 1) w_store(pc + 2);
-                if (pc + 2 <= pb) w_load(min(pc + 3, nz - 1));
-                t_load(pc + 1);
-            }
+            // the loads are clamped into the volume and issued unconditionally (a few
+            // unused planes at the chunk end) so that no register copies are needed
+            if (pc + 1 <= pb && pc + 2 <= nz - 1) w_store(pc + 2);
+            w_load(min(pc + 3, nz - 1));
+            t_load(min(pc + 1, nz - 1));
             __syncthreads();
             for (int c = tid; c < HT * kTileX; c += NT) {
                 const int r = c / kTileX, q = c - r * kTileX;
@@ -753,7 +748,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             }
             if (out) {
                 u_store(z + 1);
-                if (z + 2 <= z1) u_load(z + 2);
+                u_load(z + 2);
             }
             __syncthreads();
 #pragma unroll
@@ -771,7 +766,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             if (out) {
                 __syncthreads();
                 u_store(z + 1);
-                if (z + 2 <= z1) u_load(z + 2);
+                u_load(z + 2);
                 __syncthreads();
             }
         }

@@ -23,6 +23,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -52,7 +54,44 @@ WORKLOADS = {
                   "iterations, DVF sigma 1.5", lambda P: P.head_neck_pair()),
     "plain": ("nested-ellipsoid phantom 64x64x32, 1 structure, 1 level x 100 iterations",
               lambda P: P.plain_pair()),
+    "pelvis_slab": ("one GPU's z-slab of the pelvis-like CT when one volume is split over 8 GPUs: "
+                    "512x512x16 plus 4-plane halos (512x512x24), 8 structures, finest level x 150 "
+                    "iterations, DVF sigma 1", lambda P: slab_of(P.pelvis_pair(), 16, 4)),
 }
+
+
+def slab_of(pair, planes, halo):
+    """The middle z-slab of a pair (planes + halo on each side), finest level only: the shape
+    one GPU would hold if the volume were split in z."""
+    nz = pair.target.shape[0]
+    z0 = max(0, (nz - planes) // 2 - halo)
+    z1 = min(nz, z0 + planes + 2 * halo)
+    sl = slice(z0, z1)
+    pair.target = np.ascontiguousarray(pair.target[sl])
+    pair.moving = np.ascontiguousarray(pair.moving[sl])
+    pair.target_masks = np.ascontiguousarray(pair.target_masks[:, sl])
+    pair.moving_masks = np.ascontiguousarray(pair.moving_masks[:, sl])
+    pair.levels = 1
+    pair.iters = (pair.iters[0],)
+    pair.name = pair.name + "_slab"
+    return pair
+
+
+def copy_peak_gbs(torch, mib=1024, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes per second) with HIP events."""
+    n = mib << 18
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
 def log(msg):
@@ -99,9 +138,10 @@ def cpu_baseline(pair, seconds_hint=20.0):
                       % (pair.dims + (it, pair.levels, vi / 1e6, dt))}
 
 
-def served(ctx_cls, cgdir, P, torch, duration, rate, pool_bytes, distinct):
+def served(cgdir, P, torch, duration, rate, pool_bytes, distinct):
     """Open-loop Poisson arrivals; each request registers a pair drawn like the batched
-    workload (a pool of `distinct` pre-generated pairs is cycled)."""
+    workload (a pool of `distinct` pre-generated pairs is cycled).  The same arrival schedule
+    is replayed twice: with continuous batching (8 slots) and as a serial FIFO (1 slot)."""
     times, specs = P.serve_schedule(rate=rate, duration=duration)
     pool_specs = specs[:distinct]
     pairs = [P.from_spec(s) for s in pool_specs]
@@ -111,35 +151,41 @@ def served(ctx_cls, cgdir, P, torch, duration, rate, pool_bytes, distinct):
              for p in pairs]
     outs = [torch.empty((3,) + p.target.shape, device=dev) for p in pairs]
     prms = [cgdir.params_for_pair(p) for p in pairs]
-    lat = []
-    with ctx_cls(pool_bytes, max_slots=8) as ctx:
-        # one-at-a-time reference on the same GPU
-        t0 = time.time()
-        for it, pr, o in zip(items, prms, outs):
-            ctx.register(*it, pr, o)
-        serial_s = (time.time() - t0) / len(items)
-        start = time.time()
-        tickets = []
-        for i, t in enumerate(times):
-            now = time.time() - start
-            if t > now:
-                time.sleep(t - now)
-            j = i % len(items)
-            tickets.append(ctx.submit(*items[j], prms[j], torch.empty_like(outs[j])))
-        for t in tickets:
-            rc = ctx.wait(t)
-            if rc != cgdir.OK:
-                raise RuntimeError("served request failed: %s" % cgdir.strerror(rc))
-        end = time.time()
-        for t in tickets:
-            st = ctx.poll(t)
-            lat.append((st.t_done_ns - st.t_submit_ns) / 1e6)
-    import numpy as np
-    lat = np.array(lat)
-    return {"requests": len(lat), "rate_per_s": rate, "duration_s": duration,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "registrations_per_s": len(lat) / (end - start),
-            "serial_ms_per_registration": serial_s * 1e3, "distinct_pairs": len(items)}
+
+    def replay(slots):
+        lat = []
+        with cgdir.Context(pool_bytes, max_slots=slots) as ctx:
+            for it, pr, o in zip(items, prms, outs):   # warm-up: tile shapes tuned
+                ctx.register(*it, pr, o)
+            start = time.time()
+            tickets = []
+            for i, t in enumerate(times):
+                now = time.time() - start
+                if t > now:
+                    time.sleep(t - now)
+                j = i % len(items)
+                # requests for the same pair share its output tensor: they carry the same
+                # inputs, so whatever overlaps writes the same values
+                tickets.append(ctx.submit(*items[j], prms[j], outs[j]))
+            for t in tickets:
+                rc = ctx.wait(t)
+                if rc != cgdir.OK:
+                    raise RuntimeError("served request failed: %s" % cgdir.strerror(rc))
+            end = time.time()
+            for t in tickets:
+                st = ctx.poll(t)
+                lat.append((st.t_done_ns - st.t_submit_ns) / 1e6)
+        lat = np.array(lat)
+        return {"slots": slots, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)),
+                "registrations_per_s": len(lat) / (end - start)}
+
+    log("served: continuous batching")
+    cont = replay(8)
+    log("served: serial FIFO")
+    fifo = replay(1)
+    return {"requests": len(times), "rate_per_s": rate, "duration_s": duration,
+            "distinct_pairs": len(items), "continuous_batching": cont, "serial_fifo": fifo}
 
 
 def batched(cgdir, P, torch, n_pairs):
@@ -187,6 +233,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0, metavar="PAIRS",
                     help="also run the uneven batched workload with this many pairs (32 in full)")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -251,8 +298,11 @@ def main():
     avg_ms = s["total_ms"] / s["launches"]
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     traffic = read_traffic(args.workload, dom)
+    log("copy probe")
+    copy_gbs = copy_peak_gbs(torch)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "copy_measured_gbs": round(copy_gbs, 1),
                 "kernel": "%s (%s), finest level" % (dom, KERNEL_SYMBOL[dom]),
                 "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": per_launch_bytes,
                 "bytes_per_voxel": bpv}
@@ -285,7 +335,7 @@ def main():
         result["batched"] = batched(cgdir, P, torch, args.batch)
     if args.serve:
         log("served workload")
-        result["served"] = served(cgdir.Context, cgdir, P, torch, args.serve_seconds, 4.0,
+        result["served"] = served(cgdir, P, torch, args.serve_seconds, args.serve_rate,
                                   32 << 30, 16)
     print(json.dumps(result), flush=True)
 

@@ -117,11 +117,10 @@ def read_traffic(workload, kernel):
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(pair, seconds_hint=20.0):
-    """The oracle's Algorithm A on the full-size inputs of the workload, with 3 iterations
-    per level instead of the workload's counts."""
+def cpu_baseline(pair, it=8):
+    """The oracle's Algorithm A on the full-size inputs of the workload, with `it` iterations
+    per level instead of the workload's counts (about 15 s of work on 16 cores)."""
     import oracle
-    it = 3
     prm = oracle.params_for(pair, iters=(it,) * pair.levels)
     t0 = time.time()
     oracle.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks, prm)

@@ -220,6 +220,54 @@ typedef struct cgdir_kernel_stat {
 } cgdir_kernel_stat;
 int cgdir_kernel_stats(cgdir_ctx *ctx, cgdir_kernel_stat *out, int cap, int reset);
 
+/* ---- evaluation of a registration result (section 2.3) ----------------------------------
+ * The paper assesses a field three ways, all computed here on the device:
+ *  - intensity: RMS-ID = sqrt(mean((I0~ - T0)^2)) and Pearson's correlation coefficient CC
+ *    between the deformed moving image I0~ = I0 o u (trilinear, clamped) and the target, over
+ *    the whole volume and over the UROI (target structures dilated by uroi_margin);
+ *  - volume overlap: DSC = 2 |V_D and V_T| / (|V_D| + |V_T|) with V_D the deformed structure
+ *    (mask warp, as CGDIR_WARP_MASK) and V_T the target structure;
+ *  - contours, by volume deformation: V_D is opened (opening_radius erosions, then as many
+ *    dilations, by the 6-connected cross; outside the volume counts as outside) to remove
+ *    small islands, and its boundary (voxels with a face neighbour outside the set) is the
+ *    propagated contour.  SSD of a contour voxel = shortest Euclidean distance in mm to a
+ *    voxel of the target surface (the boundary of V_T), voxel centres scaled by spacing;
+ *    reported as mean, standard deviation (population) and 95th percentile (linear
+ *    interpolation between order statistics). */
+typedef struct cgdir_eval_params {
+    float spacing[3];    /* voxel size in mm along x, y, z; default 1.97, 1.97, 2.5 */
+    int opening_radius;  /* 0..16; default 1 */
+    int uroi_margin[3];  /* 0..8 voxels per axis; default {5, 5, 4} */
+} cgdir_eval_params;
+
+typedef struct cgdir_eval {
+    double rms_id, cc;             /* whole volume (HU; dimensionless) */
+    double rms_id_uroi, cc_uroi;   /* over the UROI; NaN when k = 0 */
+    int64_t voxels, uroi_voxels;
+    int k;
+    int64_t deformed_voxels[CGDIR_MAX_STRUCTS];  /* |V_D| */
+    int64_t target_voxels[CGDIR_MAX_STRUCTS];    /* |V_T| */
+    int64_t overlap_voxels[CGDIR_MAX_STRUCTS];   /* |V_D and V_T| */
+    double dsc[CGDIR_MAX_STRUCTS];               /* NaN when both volumes are empty */
+    int64_t contour_points[CGDIR_MAX_STRUCTS];   /* voxels of the propagated contour */
+    int64_t surface_points[CGDIR_MAX_STRUCTS];   /* voxels of the target surface */
+    double ssd_mean[CGDIR_MAX_STRUCTS];          /* mm; NaN when a contour or surface is empty */
+    double ssd_sd[CGDIR_MAX_STRUCTS];
+    double ssd_p95[CGDIR_MAX_STRUCTS];
+} cgdir_eval;
+
+void cgdir_eval_params_default(cgdir_eval_params *ep);
+
+/* Evaluate the field dvf ([3][nz][ny][nx] FP32, voxel units, target grid, host or device per
+ * dvf_where) that registers `moving` to `target` (same dims).  Masks as in cgdir_register
+ * (k may be 0: intensity metrics only).  Blocking; serialises with the context's other
+ * launches; scratch (about 12 bytes per voxel plus the contour point lists, and copies of
+ * host inputs) comes from the context pool and is released before return.  The caller owns
+ * every buffer.  Errors: CGDIR_E_INVAL (arguments), CGDIR_E_NOMEM (pool), CGDIR_E_HIP. */
+int cgdir_evaluate(cgdir_ctx *ctx, const cgdir_volume *target, const cgdir_volume *moving,
+                   const cgdir_masks *target_masks, const cgdir_masks *moving_masks,
+                   const float *dvf, int dvf_where, const cgdir_eval_params *ep, cgdir_eval *out);
+
 #ifdef __cplusplus
 }
 #endif

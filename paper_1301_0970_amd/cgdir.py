@@ -95,7 +95,27 @@ class kernel_stat(ctypes.Structure):
 
 SYMBOLS = ["cgdir_params_default", "cgdir_create", "cgdir_destroy", "cgdir_register",
            "cgdir_warp", "cgdir_register_batch", "cgdir_submit", "cgdir_poll", "cgdir_cancel",
-           "cgdir_wait", "cgdir_footprint", "cgdir_strerror", "cgdir_kernel_stats"]
+           "cgdir_wait", "cgdir_footprint", "cgdir_strerror", "cgdir_kernel_stats",
+           "cgdir_eval_params_default", "cgdir_evaluate"]
+
+
+class eval_params(ctypes.Structure):
+    _fields_ = [("spacing", ctypes.c_float * 3), ("opening_radius", ctypes.c_int),
+                ("uroi_margin", ctypes.c_int * 3)]
+
+
+_S = MAX_STRUCTS
+
+
+class eval_result(ctypes.Structure):
+    _fields_ = [("rms_id", ctypes.c_double), ("cc", ctypes.c_double),
+                ("rms_id_uroi", ctypes.c_double), ("cc_uroi", ctypes.c_double),
+                ("voxels", ctypes.c_int64), ("uroi_voxels", ctypes.c_int64), ("k", ctypes.c_int),
+                ("deformed_voxels", ctypes.c_int64 * _S), ("target_voxels", ctypes.c_int64 * _S),
+                ("overlap_voxels", ctypes.c_int64 * _S), ("dsc", ctypes.c_double * _S),
+                ("contour_points", ctypes.c_int64 * _S), ("surface_points", ctypes.c_int64 * _S),
+                ("ssd_mean", ctypes.c_double * _S), ("ssd_sd", ctypes.c_double * _S),
+                ("ssd_p95", ctypes.c_double * _S)]
 
 
 def _load():
@@ -122,8 +142,13 @@ def _load():
     lib.cgdir_strerror.argtypes = [ctypes.c_int]
     lib.cgdir_strerror.restype = ctypes.c_char_p
     lib.cgdir_kernel_stats.argtypes = [ctypes.c_void_p, P(kernel_stat), ctypes.c_int, ctypes.c_int]
+    lib.cgdir_eval_params_default.argtypes = [P(eval_params)]
+    lib.cgdir_eval_params_default.restype = None
+    lib.cgdir_evaluate.argtypes = [ctypes.c_void_p, P(volume), P(volume), P(masks), P(masks),
+                                   ctypes.c_void_p, ctypes.c_int, P(eval_params), P(eval_result)]
     for name in SYMBOLS:
-        if name not in ("cgdir_params_default", "cgdir_footprint", "cgdir_strerror"):
+        if name not in ("cgdir_params_default", "cgdir_footprint", "cgdir_strerror",
+                        "cgdir_eval_params_default"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -323,6 +348,37 @@ class Context:
         if out is None:
             out = torch.empty_like(src)
         _check(warp(self.handle, self.volume(src), dvf.data_ptr(), mode, out.data_ptr()), "cgdir_warp")
+        return out
+
+    def evaluate(self, target, moving, target_masks, moving_masks, dvf, spacing=None,
+                 opening_radius=None, uroi_margin=None) -> dict:
+        """Section 2.3 metrics of the field dvf registering moving to target (RMS-ID, CC,
+        DSC, SSD statistics of the propagated contours), computed on the GPU."""
+        ep = eval_params()
+        LIB.cgdir_eval_params_default(ctypes.byref(ep))
+        if spacing is not None:
+            ep.spacing[:] = [float(v) for v in spacing]
+        if opening_radius is not None:
+            ep.opening_radius = int(opening_radius)
+        if uroi_margin is not None:
+            ep.uroi_margin[:] = [int(v) for v in uroi_margin]
+        keep = []
+        res = eval_result()
+        rc = LIB.cgdir_evaluate(self.handle, ctypes.byref(self.volume(target)), ctypes.byref(self.volume(moving)),
+                                ctypes.byref(self.masks(target_masks, keep)),
+                                ctypes.byref(self.masks(moving_masks, keep)), dvf.data_ptr(),
+                                self._where(dvf), ctypes.byref(ep), ctypes.byref(res))
+        _check(rc, "cgdir_evaluate")
+        out = {"whole": {"rms_id": res.rms_id, "cc": res.cc, "voxels": res.voxels}, "structures": []}
+        if res.k:
+            out["uroi"] = {"rms_id": res.rms_id_uroi, "cc": res.cc_uroi, "voxels": res.uroi_voxels}
+        for i in range(res.k):
+            out["structures"].append({
+                "deformed": res.deformed_voxels[i], "target": res.target_voxels[i],
+                "overlap": res.overlap_voxels[i], "dsc": res.dsc[i],
+                "ssd": {"mean": res.ssd_mean[i], "sd": res.ssd_sd[i], "p95": res.ssd_p95[i],
+                        "points": res.contour_points[i]},
+                "surface_points": res.surface_points[i]})
         return out
 
     def register_batch(self, items, prms, outs):

@@ -11,7 +11,7 @@ LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libcgdir.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["cgdir_kernels.hip", "cgdir_runtime.hip"]
+SOURCES = ["cgdir_kernels.hip", "cgdir_eval.hip", "cgdir_runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("CGDIR_ARCH", "gfx950")

@@ -131,6 +131,26 @@ hipError_t launch_dilate_bit(const uint8_t *bits, int bit, Dims d, const int mar
                              uint8_t *rowdist, uint8_t *out, hipStream_t s);
 
 
+// evaluation (cgdir_eval.hip): reductions write eval_red_blocks() block partials of NV
+// doubles each, added by the host in block order
+int eval_red_blocks();
+hipError_t launch_intensity_pass1(const float *a, const float *b, const uint8_t *region, int64_t n,
+                                  double *partials, hipStream_t s);  // NV = 6
+hipError_t launch_intensity_pass2(const float *a, const float *b, const uint8_t *region, int64_t n, double ma,
+                                  double mb, double ra, double rb, double *partials, hipStream_t s);  // NV = 8
+hipError_t launch_overlap_counts(const uint8_t *D, const uint8_t *tbits, int bit, int64_t n, double *partials,
+                                 hipStream_t s);  // NV = 3
+hipError_t launch_value_sums(const double *x, int64_t n, double mean, double *partials, hipStream_t s);  // NV = 2
+hipError_t launch_count_nonzero(const uint8_t *m, int64_t n, double *partials, hipStream_t s);  // NV = 1
+// mode 0 erosion, 1 dilation, 2 boundary, by the 6-connected cross; bit >= 0 reads a bit-plane
+hipError_t launch_cross(const uint8_t *src, int bit, Dims d, int mode, uint8_t *dst, hipStream_t s);
+hipError_t launch_ssd(const int *cpts, int nc, const int *spts, int ns, Dims d, const float spacing[3], double *out,
+                      hipStream_t s);
+// temp == nullptr: *temp_bytes receives the scratch size needed
+hipError_t select_flagged(void *temp, size_t *temp_bytes, const uint8_t *flags, int64_t n, int *out, int *count,
+                          hipStream_t s);
+hipError_t sort_doubles(void *temp, size_t *temp_bytes, const double *in, double *out, int n, hipStream_t s);
+
 // row-segment partials of the stopping metric for a volume
 inline int64_t metric_parts(Dims d) { return (int64_t)((d.nx + kTileX - 1) / kTileX) * d.ny * d.nz; }
 

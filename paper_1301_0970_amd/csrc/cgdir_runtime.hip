@@ -1397,6 +1397,221 @@ int cgdir_warp(cgdir_ctx *c, const cgdir_volume *src, const float *dvf, int mode
     return done(CGDIR_OK);
 }
 
+// ------------------------------------------------------------------ evaluation (section 2.3)
+
+void cgdir_eval_params_default(cgdir_eval_params *ep)
+{
+    if (!ep) return;
+    ep->spacing[0] = 1.97f;
+    ep->spacing[1] = 1.97f;
+    ep->spacing[2] = 2.5f;
+    ep->opening_radius = 1;
+    ep->uroi_margin[0] = 5;
+    ep->uroi_margin[1] = 5;
+    ep->uroi_margin[2] = 4;
+}
+
+namespace cgdir {
+namespace {
+
+// scratch of one evaluation call, returned to the pool on every exit
+struct Scratch {
+    Pool &pool;
+    std::vector<void *> held;
+    explicit Scratch(Pool &p) : pool(p) {}
+    ~Scratch()
+    {
+        for (void *q : held) pool.release(q);
+    }
+    void *take(size_t bytes)
+    {
+        void *q = pool.alloc(std::max<size_t>(bytes, 256));
+        if (q) held.push_back(q);
+        return q;
+    }
+};
+
+// block partials of a reduction, added on the host in block order
+int host_sums(const double *dev, int nv, double *out, hipStream_t s)
+{
+    const int nb = eval_red_blocks();
+    std::vector<double> h((size_t)nb * nv);
+    HIP_TRY(hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int q = 0; q < nv; ++q) out[q] = 0.0;
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < nv; ++q) out[q] += h[(size_t)b * nv + q];
+    return CGDIR_OK;
+}
+
+// 95th percentile of sorted values by linear interpolation between order statistics, with
+// the interpolation written from whichever end is nearer
+double p95_sorted(double lo, double hi, double g)
+{
+    const double diff = hi - lo;
+    return g >= 0.5 ? hi - diff * (1.0 - g) : lo + diff * g;
+}
+
+}  // namespace
+}  // namespace cgdir
+
+int cgdir_evaluate(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume *moving,
+                   const cgdir_masks *target_masks, const cgdir_masks *moving_masks, const float *dvf,
+                   int dvf_where, const cgdir_eval_params *ep, cgdir_eval *out)
+{
+    if (!c || !dvf || !ep || !out) return CGDIR_E_INVAL;
+    CG_TRY(check_volume(target));
+    CG_TRY(check_volume(moving));
+    if (target->nx != moving->nx || target->ny != moving->ny || target->nz != moving->nz) return CGDIR_E_INVAL;
+    int k = 0, km = 0;
+    CG_TRY(check_masks(target_masks, &k));
+    CG_TRY(check_masks(moving_masks, &km));
+    if (k != km) return CGDIR_E_INVAL;
+    if (dvf_where != CGDIR_HOST && dvf_where != CGDIR_DEVICE) return CGDIR_E_INVAL;
+    for (int a = 0; a < 3; ++a) {
+        if (!(ep->spacing[a] > 0.f) || !std::isfinite(ep->spacing[a])) return CGDIR_E_INVAL;
+        if (ep->uroi_margin[a] < 0 || ep->uroi_margin[a] > kMaxUroiMargin) return CGDIR_E_INVAL;
+    }
+    if (ep->opening_radius < 0 || ep->opening_radius > 16) return CGDIR_E_INVAL;
+
+    hipSetDevice(c->device);
+    const Dims d{target->nx, target->ny, target->nz};
+    const int64_t n = d.n();
+    const hipStream_t s = c->stream;
+    std::lock_guard<std::mutex> lg(c->launch_mu);
+    Scratch sc(c->pool);
+
+    // inputs on the device (host inputs are copied once)
+    auto dev_copy = [&](const void *src, size_t bytes, bool host) -> const void * {
+        if (!host) return src;
+        void *q = sc.take(bytes);
+        if (q && hipMemcpyAsync(q, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return nullptr;
+        return q;
+    };
+    const float *T0 = (const float *)dev_copy(target->data, n * sizeof(float), target->where == CGDIR_HOST);
+    const float *I0 = (const float *)dev_copy(moving->data, n * sizeof(float), moving->where == CGDIR_HOST);
+    const float *u = (const float *)dev_copy(dvf, 3 * n * sizeof(float), dvf_where == CGDIR_HOST);
+    if (!T0 || !I0 || !u) return CGDIR_E_NOMEM;
+    const uint8_t *tplanes[kMaxStructs] = {}, *mplanes[kMaxStructs] = {};
+    for (int i = 0; i < k; ++i) {
+        tplanes[i] = (const uint8_t *)dev_copy(target_masks->planes[i], n, target_masks->where == CGDIR_HOST);
+        mplanes[i] = (const uint8_t *)dev_copy(moving_masks->planes[i], n, moving_masks->where == CGDIR_HOST);
+        if (!tplanes[i] || !mplanes[i]) return CGDIR_E_NOMEM;
+    }
+    const int nb = eval_red_blocks();
+    float *wI = (float *)sc.take(n * sizeof(float));
+    double *parts = (double *)sc.take((size_t)nb * 8 * sizeof(double));
+    uint8_t *tbits = nullptr, *uroi = nullptr, *rowdist = nullptr;
+    uint8_t *D = nullptr, *E = nullptr, *O = nullptr, *BD = nullptr, *BT = nullptr;
+    if (!wI || !parts) return CGDIR_E_NOMEM;
+    if (k > 0) {
+        tbits = (uint8_t *)sc.take(n);
+        uroi = (uint8_t *)sc.take(n);
+        rowdist = (uint8_t *)sc.take(n);
+        D = (uint8_t *)sc.take(n);
+        E = (uint8_t *)sc.take(n);
+        O = (uint8_t *)sc.take(n);
+        BD = (uint8_t *)sc.take(n);
+        BT = (uint8_t *)sc.take(n);
+        if (!tbits || !uroi || !rowdist || !D || !E || !O || !BD || !BT) return CGDIR_E_NOMEM;
+    }
+
+    // ---- intensity: deformed moving image against the target, whole volume and UROI
+    const float *u3[3] = {u, u + n, u + 2 * n};
+    HIP_TRY(launch_warp_linear(I0, d, u3, wI, s));
+    if (k > 0) {
+        HIP_TRY(launch_pack_masks(tplanes, k, n, tbits, s));
+        HIP_TRY(launch_uroi(tbits, d, ep->uroi_margin, rowdist, uroi, s));
+    }
+    double p1[6], p2[8];
+    HIP_TRY(launch_intensity_pass1(wI, T0, uroi, n, parts, s));
+    CG_TRY(host_sums(parts, 6, p1, s));
+    const double ma = p1[1] / p1[0], mb = p1[2] / p1[0];
+    const double ra = p1[3] > 0 ? p1[4] / p1[3] : 0.0, rb = p1[3] > 0 ? p1[5] / p1[3] : 0.0;
+    HIP_TRY(launch_intensity_pass2(wI, T0, uroi, n, ma, mb, ra, rb, parts, s));
+    CG_TRY(host_sums(parts, 8, p2, s));
+    const double nan = std::nan("");
+    auto corr = [&](double saa, double sbb, double sab) {
+        const double den = std::sqrt(saa * sbb);
+        return den > 0 ? sab / den : nan;
+    };
+    *out = cgdir_eval{};
+    out->k = k;
+    out->voxels = (int64_t)p1[0];
+    out->rms_id = std::sqrt(p2[0] / p1[0]);
+    out->cc = corr(p2[1], p2[2], p2[3]);
+    out->uroi_voxels = (int64_t)p1[3];
+    out->rms_id_uroi = p1[3] > 0 ? std::sqrt(p2[4] / p1[3]) : nan;
+    out->cc_uroi = p1[3] > 0 ? corr(p2[5], p2[6], p2[7]) : nan;
+
+    // ---- structures: overlap, propagated contour, surface distances
+    size_t sel_bytes = 0;
+    HIP_TRY(select_flagged(nullptr, &sel_bytes, BD, n, nullptr, nullptr, s));
+    for (int i = 0; i < k; ++i) {
+        out->dsc[i] = out->ssd_mean[i] = out->ssd_sd[i] = out->ssd_p95[i] = nan;
+        HIP_TRY(launch_warp_mask(mplanes[i], d, u3, D, s));
+        double cnt[3];
+        HIP_TRY(launch_overlap_counts(D, tbits, i, n, parts, s));
+        CG_TRY(host_sums(parts, 3, cnt, s));
+        out->deformed_voxels[i] = (int64_t)cnt[0];
+        out->target_voxels[i] = (int64_t)cnt[1];
+        out->overlap_voxels[i] = (int64_t)cnt[2];
+        if (cnt[0] + cnt[1] > 0) out->dsc[i] = 2.0 * cnt[2] / (cnt[0] + cnt[1]);
+        // opening: r erosions then r dilations, ping-pong between E and O
+        const uint8_t *cur = D;
+        for (int r = 0; r < 2 * ep->opening_radius; ++r) {
+            uint8_t *dst = (cur == E) ? O : E;
+            HIP_TRY(launch_cross(cur, -1, d, r < ep->opening_radius ? 0 : 1, dst, s));
+            cur = dst;
+        }
+        HIP_TRY(launch_cross(cur, -1, d, 2, BD, s));
+        HIP_TRY(launch_cross(tbits, i, d, 2, BT, s));
+        double nc = 0, ns = 0;
+        HIP_TRY(launch_count_nonzero(BD, n, parts, s));
+        CG_TRY(host_sums(parts, 1, &nc, s));
+        HIP_TRY(launch_count_nonzero(BT, n, parts, s));
+        CG_TRY(host_sums(parts, 1, &ns, s));
+        out->contour_points[i] = (int64_t)nc;
+        out->surface_points[i] = (int64_t)ns;
+        if (nc == 0 || ns == 0) continue;
+        const int ncp = (int)nc, nsp = (int)ns;
+        size_t sort_bytes = 0;
+        HIP_TRY(sort_doubles(nullptr, &sort_bytes, nullptr, nullptr, ncp, s));
+        Scratch lists(c->pool);
+        int *cpts = (int *)lists.take((size_t)ncp * sizeof(int));
+        int *spts = (int *)lists.take((size_t)nsp * sizeof(int));
+        double *dist = (double *)lists.take((size_t)ncp * sizeof(double));
+        double *sorted = (double *)lists.take((size_t)ncp * sizeof(double));
+        int *count = (int *)lists.take(sizeof(int));
+        void *temp = lists.take(std::max(sel_bytes, sort_bytes));
+        if (!cpts || !spts || !dist || !sorted || !count || !temp) return CGDIR_E_NOMEM;
+        size_t tb = sel_bytes;
+        HIP_TRY(select_flagged(temp, &tb, BD, n, cpts, count, s));
+        tb = sel_bytes;
+        HIP_TRY(select_flagged(temp, &tb, BT, n, spts, count, s));
+        HIP_TRY(launch_ssd(cpts, ncp, spts, nsp, d, ep->spacing, dist, s));
+        tb = sort_bytes;
+        HIP_TRY(sort_doubles(temp, &tb, dist, sorted, ncp, s));
+        double sums[2];
+        HIP_TRY(launch_value_sums(sorted, ncp, 0.0, parts, s));
+        CG_TRY(host_sums(parts, 2, sums, s));
+        const double mean = sums[0] / ncp;
+        HIP_TRY(launch_value_sums(sorted, ncp, mean, parts, s));
+        CG_TRY(host_sums(parts, 2, sums, s));
+        out->ssd_mean[i] = mean;
+        out->ssd_sd[i] = std::sqrt(sums[1] / ncp);
+        const double h = (double)(ncp - 1) * 0.95;
+        const int lo = (int)std::floor(h), hi = std::min(lo + 1, ncp - 1);
+        double v[2];
+        HIP_TRY(hipMemcpyAsync(&v[0], sorted + lo, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&v[1], sorted + hi, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        out->ssd_p95[i] = p95_sorted(v[0], v[1], h - lo);
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return CGDIR_OK;
+}
+
 int cgdir_submit(cgdir_ctx *c, const cgdir_request *req, uint64_t *ticket)
 {
     if (!c || !req || !ticket) return CGDIR_E_INVAL;

@@ -1,0 +1,117 @@
+"""cgdir_evaluate (section 2.3 metrics on the GPU) against the evaluation oracle.
+
+Integer results (voxel counts, contour and surface points) and the DSC built from them are
+compared exactly: the inside decision of the mask warp is taken in FP32 on both sides.  The
+surface distances are the same FP64 expression on both sides, so their statistics agree to
+rounding of the sums (1e-12).  RMS-ID and CC use the FP32 warp on the GPU and the FP64 warp in
+the oracle: relative 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1301_0970_amd import phantom as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1301_0970_amd import cgdir
+    c = cgdir.Context(2 << 30)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def compare(got, ref):
+    for reg in ("whole", "uroi"):
+        if reg not in ref:
+            continue
+        assert got[reg]["voxels"] == ref[reg]["voxels"], reg
+        assert got[reg]["rms_id"] == pytest.approx(ref[reg]["rms_id"], rel=1e-5, abs=1e-6), reg
+        assert got[reg]["cc"] == pytest.approx(ref[reg]["cc"], rel=1e-5), reg
+    assert len(got["structures"]) == len(ref["structures"])
+    for i, (g, r) in enumerate(zip(got["structures"], ref["structures"])):
+        assert (g["deformed"], g["target"], g["overlap"]) == (r["deformed"], r["target"], r["overlap"]), i
+        assert g["dsc"] == r["dsc"], i
+        assert g["ssd"]["points"] == r["ssd"]["points"], i
+        for key in ("mean", "sd", "p95"):
+            if np.isnan(r["ssd"][key]):
+                assert np.isnan(g["ssd"][key]), (i, key)
+            else:
+                assert g["ssd"][key] == pytest.approx(r["ssd"][key], rel=1e-12, abs=1e-12), (i, key)
+
+
+@pytest.mark.parametrize("case", ["registered", "random_field", "anisotropic_r2"])
+def test_evaluate_matches_oracle(ctx, case):
+    from oracle import evaluate as ev
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(72, 60, 36), amp=4.0, k=3, levels=1, iters=20, sigma=1.0, seed=41)
+    if case == "registered":
+        say("evaluate: registered pair")
+        u = ctx.register(dev(pair.target), dev(pair.moving), dev(pair.target_masks), dev(pair.moving_masks),
+                         cgdir.params_for_pair(pair)).cpu().numpy()
+        kw = {}
+    else:
+        say("evaluate: %s" % case)
+        u = P.random_smooth_field(pair.dims, 3.0, 17).astype(np.float32)
+        kw = {} if case == "random_field" else dict(spacing=(0.9, 1.3, 3.1), opening_radius=2,
+                                                      uroi_margin=(3, 2, 1))
+    got = ctx.evaluate(dev(pair.target), dev(pair.moving), dev(pair.target_masks), dev(pair.moving_masks),
+                       dev(u), **kw)
+    ref = ev.evaluate(pair.target, pair.moving, pair.target_masks, pair.moving_masks, u,
+                      spacing=kw.get("spacing", ev.DEFAULT_SPACING), radius=kw.get("opening_radius", 1),
+                      margin=kw.get("uroi_margin", (5, 5, 4)))
+    assert all(s["ssd"]["points"] > 0 for s in ref["structures"])
+    compare(got, ref)
+
+
+def test_evaluate_identity_and_host_inputs(ctx):
+    import torch
+    pair = P.plain_pair(dims=(48, 40, 28), amp=2.0, iters=1)
+    z = np.zeros((3,) + pair.target.shape, np.float32)
+    say("evaluate: identity")
+    got = ctx.evaluate(dev(pair.target), dev(pair.target), dev(pair.target_masks), dev(pair.target_masks), dev(z))
+    assert got["whole"]["rms_id"] == 0.0 and got["whole"]["cc"] == pytest.approx(1.0, rel=1e-12)
+    assert got["structures"][0]["dsc"] == 1.0
+    say("evaluate: host inputs")
+    u = P.random_smooth_field(pair.dims, 2.0, 3).astype(np.float32)
+    gd = ctx.evaluate(dev(pair.target), dev(pair.moving), dev(pair.target_masks), dev(pair.moving_masks), dev(u))
+    gh = ctx.evaluate(torch.from_numpy(pair.target), torch.from_numpy(pair.moving),
+                      torch.from_numpy(pair.target_masks), torch.from_numpy(pair.moving_masks), torch.from_numpy(u))
+    assert gd == gh
+
+
+def test_evaluate_without_structures_and_invalid_arguments(ctx):
+    from oracle import evaluate as ev
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair(dims=(40, 36, 20), amp=2.0, iters=1)
+    u = P.random_smooth_field(pair.dims, 2.0, 4).astype(np.float32)
+    say("evaluate: k = 0")
+    got = ctx.evaluate(dev(pair.target), dev(pair.moving), None, None, dev(u))
+    ref = ev.evaluate(pair.target, pair.moving, pair.target_masks[:0], pair.moving_masks[:0], u)
+    assert "uroi" not in got and got["structures"] == []
+    compare(got, ref)
+    say("evaluate: invalid arguments")
+    t, m = dev(pair.target), dev(pair.moving)
+    tm, mm = dev(pair.target_masks), dev(pair.moving_masks)
+    for bad in (dict(spacing=(0.0, 1.0, 1.0)), dict(opening_radius=-1), dict(uroi_margin=(9, 0, 0))):
+        with pytest.raises(cgdir.CgdirError) as e:
+            ctx.evaluate(t, m, tm, mm, dev(u), **bad)
+        assert e.value.code == cgdir.E_INVAL, bad
+    with pytest.raises(cgdir.CgdirError) as e:
+        ctx.evaluate(t, m[:10], tm, mm, dev(u))
+    assert e.value.code == cgdir.E_INVAL
+    with pytest.raises(cgdir.CgdirError) as e:
+        ctx.evaluate(t, m, tm, None, dev(u))
+    assert e.value.code == cgdir.E_INVAL

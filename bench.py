@@ -187,6 +187,39 @@ def served(cgdir, P, torch, duration, rate, pool_bytes, distinct):
             "distinct_pairs": len(items), "continuous_batching": cont, "serial_fifo": fifo}
 
 
+def evaluated(cgdir, torch, pair, pool):
+    """Section 2.3 metrics on the GPU for the workload registered with CG-DIR and with plain
+    demons (contour terms off): the comparison the paper makes, on the synthetic pair."""
+    dev = torch.device("cuda")
+    t = torch.from_numpy(pair.target).to(dev)
+    m = torch.from_numpy(pair.moving).to(dev)
+    tm = torch.from_numpy(pair.target_masks).to(dev)
+    mm = torch.from_numpy(pair.moving_masks).to(dev)
+    out = {}
+    with cgdir.Context(pool) as ctx:
+        for name, mask in (("cg_dir", 1), ("demons", 0)):
+            u = ctx.register(t, m, tm, mm, cgdir.params_for_pair(pair, contour_level_mask=mask))
+            ctx.evaluate(t, m, tm, mm, u)               # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.evaluate(t, m, tm, mm, u)
+            ms = (time.perf_counter() - t0) * 1e3
+            st = r["structures"]
+            out[name] = {"rms_id": r["whole"]["rms_id"], "cc": r["whole"]["cc"],
+                         "rms_id_uroi": r["uroi"]["rms_id"], "cc_uroi": r["uroi"]["cc"],
+                         "dsc": [round(x["dsc"], 4) for x in st],
+                         "ssd_mean_mm": [round(x["ssd"]["mean"], 3) for x in st],
+                         "ssd_p95_mm": [round(x["ssd"]["p95"], 3) for x in st],
+                         "evaluate_ms": ms}
+        # before registration
+        z = torch.zeros((3,) + tuple(pair.target.shape), device=dev)
+        r = ctx.evaluate(t, m, tm, mm, z)
+        out["unregistered"] = {"rms_id": r["whole"]["rms_id"], "cc": r["whole"]["cc"],
+                               "rms_id_uroi": r["uroi"]["rms_id"], "cc_uroi": r["uroi"]["cc"],
+                               "dsc": [round(x["dsc"], 4) for x in r["structures"]]}
+    return out
+
+
 def batched(cgdir, P, torch, n_pairs):
     """The uneven batch (sizes and structure counts drawn per pair): all pairs in one
     cgdir_register_batch call vs the same pairs registered one at a time."""
@@ -232,6 +265,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0, metavar="PAIRS",
                     help="also run the uneven batched workload with this many pairs (32 in full)")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--evaluate", action="store_true",
+                    help="also evaluate (section 2.3 metrics) CG-DIR against plain demons on the workload")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates HBM byte counters)")
@@ -329,6 +364,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(pair)
+    if args.evaluate:
+        log("evaluation")
+        result["evaluation"] = evaluated(cgdir, torch, pair, pool + (1 << 30))
     if args.batch:
         log("batched workload")
         result["batched"] = batched(cgdir, P, torch, args.batch)

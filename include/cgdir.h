@@ -121,7 +121,10 @@ typedef struct cgdir_params {
 
 /* Stopping rule (section 2.2, delta = RMS intensity difference over the UROI, l = change of
  * delta): the finest level stops after iteration n when (n + 1) is a multiple of
- * stop_window, n >= stop_window and delta_{n - stop_window} - delta_n <= stop_eps. */
+ * stop_window, n >= stop_window and delta_{n - stop_window} - delta_n <= stop_eps.  The rule
+ * is evaluated on the device, inside the kernel that reduces delta; the launches of later
+ * iterations then do nothing for that registration, and the host learns of the stop from
+ * a non-blocking copy every stop_window iterations (no host round trip on the path). */
 
 void cgdir_params_default(cgdir_params *p);
 

@@ -54,11 +54,13 @@ struct StepArgs {
     int k;                    // active structures (<= kMaxStructs)
     float lam[kMaxStructs];   // lambda_i
     float lam_sum;            // lambda_0 + ... + lambda_{k-1}, summed in this order
-    float hs[kMaxStructs];    // s_i / 2
+    uint32_t neg;             // bit i: s_i = -1 (else +1); the modified images use s_i / 2
     float c0;                 // CT-number offset
     float inv_norm;           // 1 / norm_range
     float w[kMaxRadius + 1];  // fluid Gaussian: w[0] centre, w[m] = weight at +-m
     int tz;                   // planes per block (z chunk)
+    const int *stop;          // iterations after which the pair stopped (0: running)
+    int iter;                 // this launch's iteration: nothing to do once *stop <= iter
 };
 
 // Arguments of the smoothing of u_c into u (diffusion Gaussian), followed by the warp of I0
@@ -70,14 +72,24 @@ struct SmoothArgs {
     float w[kMaxRadius + 1];  // w[0] centre, w[m] = weight at +-m
     int tz;
     WarpArgs warp;            // where the warp goes
+    const int *stop;          // iterations after which the pair stopped (0: running)
+    int iter;                 // this launch's iteration: nothing to do once *stop <= iter
 };
 
 // One pair's stopping-metric reduction in a batched finalize.
+// delta_n = sqrt(sum of partials / count) goes to hist[n].  With window > 0 the stopping
+// rule is applied on the device: after iteration n with (n + 1) % window == 0 and
+// n >= window, the pair stops when hist[n - window] - delta_n <= eps, and *stop receives
+// n + 1 (the iterations run).  Once *stop is set nothing more is recorded.
 struct DeltaJob {
     const float *partials;
     int nparts;
+    int n;
     const int64_t *count;
-    double *out;
+    double *hist;
+    int *stop;
+    double eps;
+    int window;
 };
 
 // Batched launches: one launch over the tiles of n pairs.  The descriptors travel in the

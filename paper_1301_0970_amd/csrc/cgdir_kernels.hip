@@ -278,9 +278,10 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
             const float gky = 0.5f * ((f[4] ? ldg(K, gx + nx * yp + nxy * gz) : 0.f) - (f[3] ? ldg(K, gx + nx * ym + nxy * gz) : 0.f));
             const float gkz = 0.5f * ((f[6] ? ldg(K, gx + nx * gy + nxy * zp) : 0.f) - (f[5] ? ldg(K, gx + nx * gy + nxy * zm) : 0.f));
             const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
-            const float ai = __builtin_fmaf(a.hs[i], proj, a0);
+            const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
+            const float ai = __builtin_fmaf(hs, proj, a0);
             const float ni = (tb & kb) ? t0 + a.c0 : 0.f;
-            const float di = __builtin_fmaf(a.hs[i], ni - Kc, d);
+            const float di = __builtin_fmaf(hs, ni - Kc, d);
             const float la = a.lam[i] * ai;
             num = __builtin_fmaf(la, di, num);
             den = __builtin_fmaf(la, ai, den);
@@ -312,9 +313,10 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
                         else gkz -= hK;
                     }
                     const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
-                    const float ai = __builtin_fmaf(a.hs[i], proj, a0);
+                    const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
+                    const float ai = __builtin_fmaf(hs, proj, a0);
                     const float ni = (tb & bit) ? tc0 : 0.f;
-                    const float di = __builtin_fmaf(a.hs[i], ni - Kc, d);
+                    const float di = __builtin_fmaf(hs, ni - Kc, d);
                     const float la = a.lam[i] * ai;
                     num = __builtin_fmaf(la, di, num);
                     den = __builtin_fmaf(la, ai, den);
@@ -507,6 +509,10 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
 {
     const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
     const int q = pair_of(b.prefix, b.n, L);
+    if (b.d[q].stop) {  // the pair stopped after an earlier iteration: nothing to do
+        const int s = *b.d[q].stop;
+        if (s != 0 && s <= b.d[q].iter) return;
+    }
     smooth_tile<R, TY>(b.d[q], L - b.prefix[q]);
 }
 
@@ -817,6 +823,10 @@ __global__ void __launch_bounds__(kTileX *TY) k_step_batch(StepBatch b)
 {
     const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
     const int q = pair_of(b.prefix, b.n, L);
+    if (b.d[q].stop) {  // the pair stopped after an earlier iteration: nothing to do
+        const int s = *b.d[q].stop;
+        if (s != 0 && s <= b.d[q].iter) return;
+    }
     step_tile<R, TY>(b.d[q], L - b.prefix[q]);
 }
 
@@ -841,6 +851,7 @@ __global__ void __launch_bounds__(256) k_warp_init(WarpArgs w, Field3 u)
 __global__ void __launch_bounds__(256) k_delta_finalize_batch(DeltaBatch b)
 {
     const DeltaJob &j = b.d[blockIdx.x];
+    if (j.stop && *j.stop) return;  // stopped at an earlier iteration
     __shared__ double red[256];
     double s = 0.0;
     for (int i = threadIdx.x; i < j.nparts; i += 256) s += (double)j.partials[i];
@@ -851,8 +862,13 @@ __global__ void __launch_bounds__(256) k_delta_finalize_batch(DeltaBatch b)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const int64_t n = *j.count;
-        j.out[0] = n > 0 ? sqrt(red[0] / (double)n) : 0.0;
+        const int64_t c = *j.count;
+        const double delta = c > 0 ? sqrt(red[0] / (double)c) : 0.0;
+        j.hist[j.n] = delta;
+        // stopping rule on the device: delta_{n-W} - delta_n <= eps after every W iterations
+        if (j.window > 0 && (j.n + 1) % j.window == 0 && j.n - j.window >= 0 &&
+            j.hist[j.n - j.window] - delta <= j.eps)
+            *j.stop = j.n + 1;
     }
 }
 

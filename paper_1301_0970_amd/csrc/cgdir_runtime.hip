@@ -302,6 +302,13 @@ using namespace cgdir;
 
 struct Job;
 
+// pinned host record through which the host follows a job's progress without blocking
+struct PinRec {
+    int stop;      // finest-level iterations run when the stopping rule fired, else 0
+    int pad;
+    double delta;  // a recent delta
+};
+
 struct cgdir_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -338,6 +345,31 @@ struct cgdir_ctx {
     struct Request;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     std::mutex launch_mu;  // keeps each job's launch sequence contiguous on the stream
+
+    // pinned records, allocated in chunks and recycled
+    std::mutex pin_mu;
+    std::vector<PinRec *> pin_chunks, pin_free;
+    PinRec *take_pin()
+    {
+        std::lock_guard<std::mutex> g(pin_mu);
+        if (pin_free.empty()) {
+            constexpr int kChunk = 256;
+            PinRec *chunk = nullptr;
+            if (hipHostMalloc((void **)&chunk, kChunk * sizeof(PinRec), hipHostMallocDefault) != hipSuccess)
+                return nullptr;
+            pin_chunks.push_back(chunk);
+            for (int i = kChunk - 1; i >= 0; --i) pin_free.push_back(chunk + i);
+        }
+        PinRec *r = pin_free.back();
+        pin_free.pop_back();
+        *r = PinRec{};
+        return r;
+    }
+    void give_pin(PinRec *r)
+    {
+        std::lock_guard<std::mutex> g(pin_mu);
+        pin_free.push_back(r);
+    }
 };
 
 namespace cgdir {
@@ -498,6 +530,11 @@ struct Job {
     int64_t *misc_i64 = nullptr;  // [0] UROI count, [1..] reduction partials
     double *misc_f64 = nullptr;
     int *flag = nullptr;
+    int *stop_dev = nullptr;      // device: finest-level iterations run when the rule fired
+    PinRec *pin = nullptr;        // pinned copies of stop_dev and of a recent delta
+    hipEvent_t pin_ev = nullptr;
+    bool pin_busy = false;        // a copy into pin is in flight behind pin_ev
+    double last_delta = 0.0;
     double *sign_parts = nullptr;
 
     // progress
@@ -506,7 +543,6 @@ struct Job {
     bool level_started = false;
     bool finished = false;
     int iters_done0 = 0;
-    std::vector<double> delta_host;
 
     size_t need() const { return footprint_bytes(d0, k, req.params, host_images, ctx->tune); }
 
@@ -553,6 +589,16 @@ struct Job {
     {
         for (void *p : allocs) ctx->pool.release(p);
         allocs.clear();
+        if (pin_ev) {
+            if (pin_busy) hipEventSynchronize(pin_ev);  // no copy may land in a recycled record
+            hipEventDestroy(pin_ev);
+            pin_ev = nullptr;
+            pin_busy = false;
+        }
+        if (pin) {
+            ctx->give_pin(pin);
+            pin = nullptr;
+        }
     }
 
     int allocate()
@@ -603,7 +649,16 @@ struct Job {
         misc_i64 = (int64_t *)misc;               // [0] count, [8, 264) count partials
         misc_f64 = (double *)(misc + 2304);        // 4 doubles
         flag = (int *)(misc + 2304 + 64);
+        stop_dev = (int *)(misc + 2304 + 96);
         sign_parts = (double *)(misc + 4096);      // 128 x 4 doubles
+        if (delta_on) {
+            pin = ctx->take_pin();
+            if (!pin || hipEventCreateWithFlags(&pin_ev, hipEventDisableTiming) != hipSuccess) {
+                pin_ev = nullptr;
+                release();
+                return CGDIR_E_HIP;
+            }
+        }
         return CGDIR_OK;
     }
 
@@ -697,6 +752,7 @@ struct Job {
             HIP_TRY(launch_fill(ubuf, 3 * n0, 0.f, s));
         }
         HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+        HIP_TRY(hipMemsetAsync(stop_dev, 0, sizeof(int), s));
         return CGDIR_OK;
     }
 
@@ -767,15 +823,18 @@ struct Job {
         sa.d = d;
         sa.k = contour ? k : 0;
         sa.lam_sum = 0.f;
+        sa.neg = 0;
         for (int i = 0; i < kMaxStructs; ++i) {
             sa.lam[i] = i < k ? lam[i] : 0.f;
-            sa.hs[i] = i < k ? hs[i] : 0.f;
+            if (i < k && hs[i] < 0.f) sa.neg |= 1u << i;
             if (i < sa.k) sa.lam_sum += sa.lam[i];
         }
         sa.c0 = req.params.intensity_offset;
         sa.inv_norm = 1.0f / req.params.norm_range;
         for (int m = 0; m <= kMaxRadius; ++m) sa.w[m] = wf[m];
         sa.tz = ctx->tune.step_tz;
+        sa.stop = delta_on ? stop_dev : nullptr;
+        sa.iter = iter;
         return sa;
     }
 
@@ -784,8 +843,12 @@ struct Job {
         DeltaJob j;
         j.partials = partials;
         j.nparts = (int)metric_parts(level_dims(d0, level));
+        j.n = iter;
         j.count = misc_i64;
-        j.out = delta_dev + iter;
+        j.hist = delta_dev;
+        j.stop = stop_dev;
+        j.eps = (double)req.params.stop_eps;
+        j.window = req.params.stop_mode ? req.params.stop_window : 0;
         return j;
     }
 
@@ -801,6 +864,8 @@ struct Job {
         sb.tz = ctx->tune.smooth_tz;
         for (int m = 0; m <= kMaxRadius; ++m) sb.w[m] = wd[m];
         sb.warp = warp_args();
+        sb.stop = delta_on ? stop_dev : nullptr;
+        sb.iter = iter;
         return sb;
     }
 
@@ -809,15 +874,6 @@ struct Job {
         const Dims d = level_dims(d0, level);
         for (int c = 0; c < 3; ++c) HIP_TRY(launch_nonfinite(comp(ubuf, c), d.n(), flag, ctx->stream));
         return CGDIR_OK;
-    }
-
-    // stopping rule at the finest level after iteration n = iter - 1
-    bool stop_due(const std::vector<double> &h) const
-    {
-        const int W = req.params.stop_window;
-        const int n = iter - 1;
-        return req.params.stop_mode && level == 0 && (n + 1) % W == 0 && n - W >= 0 &&
-               h[n - W] - h[n] <= (double)req.params.stop_eps;
     }
 
     // bring the job to a level with an iteration to run (prolongation, empty levels), or
@@ -840,24 +896,31 @@ struct Job {
         return CGDIR_OK;
     }
 
-    // bookkeeping after the iteration's launches: stopping rule (reads delta back every
-    // stop_window iterations), end of level
+    // bookkeeping after the iteration's launches.  The device applies the stopping rule
+    // (the delta kernel sets stop_dev and later launches do nothing for the job); every
+    // stop_window iterations the host queues a copy of stop_dev and of the latest delta into
+    // pinned memory and looks at it once the copy has landed, without ever waiting for it.
     int after_iteration()
     {
         ++iter;
-        bool stop = false;
-        if (req.params.stop_mode && level == 0 && iter % req.params.stop_window == 0) {
-            delta_host.resize(iter);
-            HIP_TRY(hipMemcpyAsync(delta_host.data(), delta_dev, iter * sizeof(double), hipMemcpyDeviceToHost,
-                                   ctx->stream));
-            HIP_TRY(hipStreamSynchronize(ctx->stream));
-            stop = stop_due(delta_host);
-        }
-        if (stop) {
-            CG_TRY(end_level());
-            iters_done0 = iter;
-            finished = true;
-            return CGDIR_OK;
+        if (delta_on && level == 0 && pin) {
+            if (pin_busy && hipEventQuery(pin_ev) == hipSuccess) {
+                pin_busy = false;
+                if (pin->stop) {
+                    CG_TRY(end_level());
+                    iters_done0 = pin->stop;
+                    finished = true;
+                    return CGDIR_OK;
+                }
+                last_delta = pin->delta;
+            }
+            if (!pin_busy && iter % req.params.stop_window == 0) {
+                HIP_TRY(hipMemcpyAsync(&pin->stop, stop_dev, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+                HIP_TRY(hipMemcpyAsync(&pin->delta, delta_dev + (iter - 1), sizeof(double), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+                HIP_TRY(hipEventRecord(pin_ev, ctx->stream));
+                pin_busy = true;
+            }
         }
         return prepare();
     }
@@ -874,6 +937,13 @@ struct Job {
     // after the stream has drained: host-side outputs and the non-finite check
     int conclude()
     {
+        if (delta_on) {
+            int stopped = 0;
+            HIP_TRY(hipMemcpy(&stopped, stop_dev, sizeof(int), hipMemcpyDeviceToHost));
+            if (stopped > 0) iters_done0 = stopped;  // the rule fired before the host saw it
+            if (iters_done0 > 0)
+                HIP_TRY(hipMemcpy(&last_delta, delta_dev + (iters_done0 - 1), sizeof(double), hipMemcpyDeviceToHost));
+        }
         if (delta_on && req.params.delta_hist && iters_done0 > 0) {
             HIP_TRY(hipMemcpy(req.params.delta_hist, delta_dev, iters_done0 * sizeof(double), hipMemcpyDeviceToHost));
         }
@@ -1111,7 +1181,7 @@ void scheduler(cgdir_ctx *c)
             cgdir_ctx::Request *r = active[i];
             r->level = r->job.level;
             r->iter = r->job.iter;
-            if (!r->job.delta_host.empty()) r->last_delta = r->job.delta_host.back();
+            r->last_delta = r->job.last_delta;
             if (r->emitted && (!r->done_ev || hipEventQuery(r->done_ev) == hipSuccess)) {
                 const int rc = r->error != CGDIR_OK ? r->error : r->job.conclude();
                 if (r->done_ev) spare.push_back(r->done_ev);
@@ -1258,6 +1328,7 @@ int cgdir_destroy(cgdir_ctx *c)
         std::lock_guard<std::mutex> lg(c->launch_mu);
         c->tuner.release_all();
     }
+    for (PinRec *chunk : c->pin_chunks) hipHostFree(chunk);
     if (c->own_pool) hipFree(c->own_pool);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;

@@ -155,3 +155,55 @@ def test_batch_of_many_small_pairs_spans_several_launches():
         assert rc == cgdir.OK and st == [0] * len(pairs)
         for a, o in zip(alone, outs):
             np.testing.assert_array_equal(a, o.cpu().numpy())
+
+
+def test_early_stop_on_the_device_alone_batched_and_served():
+    """The stopping rule runs on the device: each pair stops at its own iteration whether it
+    runs alone, batched or served, and the launches after its stop leave its field as it was
+    at the stop."""
+    import ctypes
+
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pairs = [P.plain_pair(dims=(64, 48, 24), amp=a, iters=60, seed=s) for a, s in ((2.0, 21), (3.0, 22), (1.5, 23))]
+    items = _items(pairs)
+    with cgdir.Context(2 << 30) as ctx:
+        say("stop: histories")
+        hist = [ctx.register(*it, prm=cgdir.params_for_pair(p), delta=True)[1] for it, p in zip(items, pairs)]
+        prog = sorted(h[m - 10] - h[m] for h in hist for m in range(19, 60, 10))
+        mid = len(prog) // 2
+        eps = 0.5 * (prog[mid - 1] + prog[mid])   # between two progress values, away from all
+        prms = [cgdir.params_for_pair(p, stop_mode=1, stop_eps=eps) for p in pairs]
+        say("stop: alone (eps %.3g)" % eps)
+        alone = [ctx.register(*it, prm=pr, delta=True) for it, pr in zip(items, prms)]
+        ns = [a[2] for a in alone]
+        assert any(n < 60 for n in ns), ns
+        for (u, h, n), hfull in zip(alone, hist):
+            np.testing.assert_array_equal(h, hfull[:n])
+            first = next((m for m in range(19, 60, 10) if h[m - 10] - h[m] <= float(np.float32(eps))), 59) \
+                if n >= 20 else n - 1
+            assert n == first + 1
+        say("stop: fixed-count reruns")
+        for it, p, (u, _, n) in zip(items, pairs, alone):
+            u_n = ctx.register(*it, prm=cgdir.params_for_pair(p, iters=(n,)))
+            np.testing.assert_array_equal(u.cpu().numpy(), u_n.cpu().numpy())
+        say("stop: batched")
+        done = [ctypes.c_int(0) for _ in pairs]
+        for pr, d in zip(prms, done):
+            pr.iters_done = ctypes.pointer(d)
+        outs = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
+        rc, st = ctx.register_batch(items, prms, outs)
+        assert rc == cgdir.OK and st == [0] * len(pairs)
+        assert [d.value for d in done] == ns
+        for (u, _, _), o in zip(alone, outs):
+            np.testing.assert_array_equal(u.cpu().numpy(), o.cpu().numpy())
+        say("stop: served")
+        for d in done:
+            d.value = 0
+        outs = [torch.empty_like(o) for o in outs]
+        tickets = [ctx.submit(*it, pr, o) for it, pr, o in zip(items, prms, outs)]
+        for t in tickets:
+            assert ctx.wait(t, int(60e9)) == cgdir.OK
+        assert [d.value for d in done] == ns
+        for (u, _, _), o in zip(alone, outs):
+            np.testing.assert_array_equal(u.cpu().numpy(), o.cpu().numpy())

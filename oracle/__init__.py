@@ -44,6 +44,7 @@ class _Params(ctypes.Structure):
         ("stop_window", ctypes.c_int),
         ("norm_range", ctypes.c_double),
         ("uroi_radius", ctypes.c_int * 3),
+        ("spacing", ctypes.c_double * 3),
     ]
 
 
@@ -64,6 +65,7 @@ class Params:
     stop_window: int = 10
     norm_range: float = 2500.0
     uroi_radius: Sequence[int] = (5, 5, 4)
+    spacing: Optional[Sequence[float]] = None   # finest voxel size (x, y, z); None = voxel units
 
     def to_c(self, k: int) -> _Params:
         p = _Params()
@@ -86,6 +88,7 @@ class Params:
         p.norm_range = float(self.norm_range)
         for i in range(3):
             p.uroi_radius[i] = int(self.uroi_radius[i])
+            p.spacing[i] = float(self.spacing[i]) if self.spacing is not None else 0.0
         return p
 
 
@@ -139,6 +142,19 @@ def smooth(f, sigma: float) -> np.ndarray:
     return out
 
 
+def smooth_axes(f, sigmas) -> np.ndarray:
+    """Separable Gaussian with its own sigma (voxels) along x, y, z."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    s = _f64(np.asarray(sigmas, float))
+    _check(lib().orc_smooth_axes(_ptr(f), *_dims(f), _ptr(s), _ptr(out)), "smooth_axes")
+    return out
+
+
+def _h(spacing):
+    return _f64(np.asarray(spacing, float)) if spacing is not None else None
+
+
 def sample(f, px, py, pz) -> float:
     f = _f64(f)
     return lib().orc_sample(_ptr(f), *_dims(f), ctypes.c_double(px), ctypes.c_double(py),
@@ -172,10 +188,12 @@ def warp_mask_f32(m, u) -> np.ndarray:
     return out
 
 
-def gradient(f) -> np.ndarray:
+def gradient(f, spacing=None) -> np.ndarray:
+    """Central differences (clamped), divided by the voxel size (x, y, z) when given."""
     f = _f64(f)
     g = np.empty((3,) + f.shape)
-    _check(lib().orc_gradient(_ptr(f), *_dims(f), _ptr(g)), "gradient")
+    h = _h(spacing)
+    _check(lib().orc_gradient_h(_ptr(f), *_dims(f), _ptr(h) if h is not None else None, _ptr(g)), "gradient")
     return g
 
 
@@ -243,7 +261,7 @@ def _ptr_array(arrs):
     return t
 
 
-def force(wI0, T0, wIp, Tp, lambdas) -> np.ndarray:
+def force(wI0, T0, wIp, Tp, lambdas, spacing=None) -> np.ndarray:
     wI0 = _f64(wI0)
     T0 = _f64(T0)
     wIp = [_f64(a) for a in wIp]
@@ -251,13 +269,14 @@ def force(wI0, T0, wIp, Tp, lambdas) -> np.ndarray:
     k = len(wIp)
     lam = _f64(np.asarray(lambdas, float).reshape(-1) if k else np.zeros(1))
     du = np.empty((3,) + wI0.shape)
-    _check(lib().orc_force(_ptr(wI0), _ptr(T0), k, _ptr_array(wIp), _ptr_array(Tp), _ptr(lam),
-                           *_dims(wI0), _ptr(du)), "force")
+    h = _h(spacing)
+    _check(lib().orc_force_h(_ptr(wI0), _ptr(T0), k, _ptr_array(wIp), _ptr_array(Tp), _ptr(lam),
+                             *_dims(wI0), _ptr(h) if h is not None else None, _ptr(du)), "force")
     return du
 
 
 def step(I0, T0, Iplus, Tplus, lambdas, sigma_f, sigma_d, u, uroi_mask=None,
-         norm_range=2500.0):
+         norm_range=2500.0, spacing=None):
     """One iteration from u (not modified); returns (u_next, delta or None)."""
     I0 = _f64(I0)
     T0 = _f64(T0)
@@ -268,8 +287,10 @@ def step(I0, T0, Iplus, Tplus, lambdas, sigma_f, sigma_d, u, uroi_mask=None,
     un = _f64(u).copy()
     delta = ctypes.c_double(0.0)
     ur = _u8(uroi_mask) if uroi_mask is not None else None
+    h = _h(spacing)
     _check(lib().orc_step(_ptr(I0), _ptr(T0), *_dims(I0), k, _ptr_array(Ip), _ptr_array(Tp),
                           _ptr(lam), ctypes.c_double(sigma_f), ctypes.c_double(sigma_d),
+                          _ptr(h) if h is not None else None,
                           _ptr(ur) if ur is not None else None, ctypes.c_double(norm_range),
                           _ptr(un), ctypes.byref(delta) if ur is not None else None), "step")
     return un, (delta.value if ur is not None else None)

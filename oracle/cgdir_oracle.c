@@ -77,22 +77,30 @@ static void smooth_axis(const double *f, int nx, int ny, int nz, int ax, const d
             }
 }
 
-int orc_smooth(const double *f, int nx, int ny, int nz, double sigma, double *out)
+int orc_smooth_axes(const double *f, int nx, int ny, int nz, const double sigma[3], double *out)
 {
     if (bad_dims(nx, ny, nz) || f == out) return -1;
-    int R = orc_gauss_radius(sigma);
-    double *w = (double *)malloc(sizeof(double) * (size_t)(2 * R + 1));
     size_t n = (size_t)nx * ny * nz;
     double *a = (double *)malloc(sizeof(double) * n);
     double *b = (double *)malloc(sizeof(double) * n);
-    orc_gauss_weights(sigma, w);
-    smooth_axis(f, nx, ny, nz, 0, w, R, a);
-    smooth_axis(a, nx, ny, nz, 1, w, R, b);
-    smooth_axis(b, nx, ny, nz, 2, w, R, out);
-    free(w);
+    const double *src[3] = {f, a, b};
+    double *dst[3] = {a, b, out};
+    for (int ax = 0; ax < 3; ++ax) {
+        int R = orc_gauss_radius(sigma[ax]);
+        double *w = (double *)malloc(sizeof(double) * (size_t)(2 * R + 1));
+        orc_gauss_weights(sigma[ax], w);
+        smooth_axis(src[ax], nx, ny, nz, ax, w, R, dst[ax]);
+        free(w);
+    }
     free(a);
     free(b);
     return 0;
+}
+
+int orc_smooth(const double *f, int nx, int ny, int nz, double sigma, double *out)
+{
+    const double s[3] = {sigma, sigma, sigma};
+    return orc_smooth_axes(f, nx, ny, nz, s, out);
 }
 
 /* ---------------------------------------------------------------- interpolation (kernel 4) */
@@ -212,24 +220,6 @@ int orc_warp_mask_f32(const uint8_t *m, int nx, int ny, int nz, const float *u, 
     return 0;
 }
 
-/* ---------------------------------------------------------------- gradient (kernel 2) */
-
-int orc_gradient(const double *f, int nx, int ny, int nz, double *g)
-{
-    if (bad_dims(nx, ny, nz)) return -1;
-    size_t n = (size_t)nx * ny * nz;
-#pragma omp parallel for schedule(static)
-    for (int l = 0; l < nz; ++l)
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                size_t v = IDX(i, j, l);
-                g[v] = 0.5 * (f[IDX(clampi(i + 1, 0, nx - 1), j, l)] - f[IDX(clampi(i - 1, 0, nx - 1), j, l)]);
-                g[n + v] = 0.5 * (f[IDX(i, clampi(j + 1, 0, ny - 1), l)] - f[IDX(i, clampi(j - 1, 0, ny - 1), l)]);
-                g[2 * n + v] = 0.5 * (f[IDX(i, j, clampi(l + 1, 0, nz - 1))] - f[IDX(i, j, clampi(l - 1, 0, nz - 1))]);
-            }
-    return 0;
-}
-
 /* ---------------------------------------------------------------- Eq.7 (kernel 3) */
 
 /* v minimising E1(v) of Eq.6 with beta = d^2 (Thirion):
@@ -245,18 +235,55 @@ double orc_eq7(double a0, double d, int k, const double *lambda, const double *a
     return num / den;
 }
 
-static void grad_at(const double *f, int nx, int ny, int nz, int i, int j, int l, double g[3])
+/* ---------------------------------------------------------------- gradient (kernel 2) */
+
+/* central differences divided by twice the voxel size h of each axis */
+static void grad_at(const double *f, int nx, int ny, int nz, int i, int j, int l, const double h[3], double g[3])
 {
-    g[0] = 0.5 * (f[IDX(clampi(i + 1, 0, nx - 1), j, l)] - f[IDX(clampi(i - 1, 0, nx - 1), j, l)]);
-    g[1] = 0.5 * (f[IDX(i, clampi(j + 1, 0, ny - 1), l)] - f[IDX(i, clampi(j - 1, 0, ny - 1), l)]);
-    g[2] = 0.5 * (f[IDX(i, j, clampi(l + 1, 0, nz - 1))] - f[IDX(i, j, clampi(l - 1, 0, nz - 1))]);
+    g[0] = (f[IDX(clampi(i + 1, 0, nx - 1), j, l)] - f[IDX(clampi(i - 1, 0, nx - 1), j, l)]) / (2.0 * h[0]);
+    g[1] = (f[IDX(i, clampi(j + 1, 0, ny - 1), l)] - f[IDX(i, clampi(j - 1, 0, ny - 1), l)]) / (2.0 * h[1]);
+    g[2] = (f[IDX(i, j, clampi(l + 1, 0, nz - 1))] - f[IDX(i, j, clampi(l - 1, 0, nz - 1))]) / (2.0 * h[2]);
+}
+
+static const double kUnit[3] = {1.0, 1.0, 1.0};
+
+int orc_gradient(const double *f, int nx, int ny, int nz, double *g)
+{
+    return orc_gradient_h(f, nx, ny, nz, NULL, g);
+}
+
+int orc_gradient_h(const double *f, int nx, int ny, int nz, const double *h, double *g)
+{
+    if (bad_dims(nx, ny, nz)) return -1;
+    if (!h) h = kUnit;
+    size_t n = (size_t)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double gv[3];
+                grad_at(f, nx, ny, nz, i, j, l, h, gv);
+                size_t v = IDX(i, j, l);
+                g[v] = gv[0];
+                g[n + v] = gv[1];
+                g[2 * n + v] = gv[2];
+            }
+    return 0;
 }
 
 int orc_force(const double *wI0, const double *T0, int k, const double *const *wIp,
               const double *const *Tp, const double *lambda, int nx, int ny, int nz,
               double *du)
 {
+    return orc_force_h(wI0, T0, k, wIp, Tp, lambda, nx, ny, nz, NULL, du);
+}
+
+int orc_force_h(const double *wI0, const double *T0, int k, const double *const *wIp,
+                const double *const *Tp, const double *lambda, int nx, int ny, int nz,
+                const double *h, double *du)
+{
     if (bad_dims(nx, ny, nz) || k < 0 || k > ORC_MAX_STRUCTS) return -1;
+    if (!h) h = kUnit;
     size_t n = (size_t)nx * ny * nz;
 #pragma omp parallel for schedule(static)
     for (int l = 0; l < nz; ++l)
@@ -264,7 +291,7 @@ int orc_force(const double *wI0, const double *T0, int k, const double *const *w
             for (int i = 0; i < nx; ++i) {
                 size_t v = IDX(i, j, l);
                 double g0[3];
-                grad_at(wI0, nx, ny, nz, i, j, l, g0);
+                grad_at(wI0, nx, ny, nz, i, j, l, h, g0);
                 double a02 = g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2];
                 if (a02 == 0.0) { /* the direction n is undefined: no displacement */
                     du[v] = du[n + v] = du[2 * n + v] = 0.0;
@@ -276,14 +303,15 @@ int orc_force(const double *wI0, const double *T0, int k, const double *const *w
                 double a[ORC_MAX_STRUCTS], di[ORC_MAX_STRUCTS];
                 for (int s = 0; s < k; ++s) {
                     double gi[3];
-                    grad_at(wIp[s], nx, ny, nz, i, j, l, gi);
+                    grad_at(wIp[s], nx, ny, nz, i, j, l, h, gi);
                     a[s] = gi[0] * nv[0] + gi[1] * nv[1] + gi[2] * nv[2];
                     di[s] = Tp[s][v] - wIp[s][v];
                 }
+                /* v n is the step in the length unit of h; the field is kept in voxels */
                 double vv = orc_eq7(a0, d, k, lambda, a, di);
-                du[v] = vv * nv[0];
-                du[n + v] = vv * nv[1];
-                du[2 * n + v] = vv * nv[2];
+                du[v] = vv * nv[0] / h[0];
+                du[n + v] = vv * nv[1] / h[1];
+                du[2 * n + v] = vv * nv[2] / h[2];
             }
     return 0;
 }
@@ -411,10 +439,14 @@ int orc_modified_image(const double *F, const uint8_t *mask, int s, double c0, s
 
 int orc_step(const double *I0, const double *T0, int nx, int ny, int nz, int k,
              const double *const *Iplus, const double *const *Tplus, const double *lambda,
-             double sigma_f, double sigma_d, const uint8_t *uroi, double norm_range,
+             double sigma_f, double sigma_d, const double *h, const uint8_t *uroi, double norm_range,
              double *u, double *delta)
 {
     if (bad_dims(nx, ny, nz) || k < 0 || k > ORC_MAX_STRUCTS) return -1;
+    if (!h) h = kUnit;
+    /* the Gaussians are given in the length unit of h: sigma / h voxels along each axis */
+    const double sf[3] = {sigma_f / h[0], sigma_f / h[1], sigma_f / h[2]};
+    const double sd[3] = {sigma_d / h[0], sigma_d / h[1], sigma_d / h[2]};
     size_t n = (size_t)nx * ny * nz;
     double *wI0 = (double *)malloc(sizeof(double) * n);
     double **wIp = (double **)malloc(sizeof(double *) * (size_t)(k > 0 ? k : 1));
@@ -441,13 +473,13 @@ int orc_step(const double *I0, const double *T0, int nx, int ny, int nz, int k,
         *delta = cnt ? sqrt(sum / (double)cnt) : 0.0;
     }
     /* step 1: gradients and Eq.7 */
-    orc_force(wI0, T0, k, (const double *const *)wIp, Tplus, lambda, nx, ny, nz, du);
+    orc_force_h(wI0, T0, k, (const double *const *)wIp, Tplus, lambda, nx, ny, nz, h, du);
     /* step 2: smooth the displacement */
-    for (int c = 0; c < 3; ++c) orc_smooth(du + c * n, nx, ny, nz, sigma_f, dus + c * n);
+    for (int c = 0; c < 3; ++c) orc_smooth_axes(du + c * n, nx, ny, nz, sf, dus + c * n);
     /* step 3: composite update */
     orc_compose(u, dus, nx, ny, nz, uc);
     /* step 4: smooth the field */
-    for (int c = 0; c < 3; ++c) orc_smooth(uc + c * n, nx, ny, nz, sigma_d, u + c * n);
+    for (int c = 0; c < 3; ++c) orc_smooth_axes(uc + c * n, nx, ny, nz, sd, u + c * n);
 
     for (int s = 0; s < k; ++s) free(wIp[s]);
     free(wIp);
@@ -534,11 +566,16 @@ int orc_register(const double *target, const double *moving, int nx, int ny, int
         }
         int fine = (lv == 0);
         int W = p->stop_window > 0 ? p->stop_window : 10;
+        /* physical voxel size of this level (the finest size doubles per level), or voxel
+           units throughout when no spacing is given */
+        double hl[3] = {1.0, 1.0, 1.0};
+        if (p->spacing[0] > 0.0)
+            for (int a = 0; a < 3; ++a) hl[a] = p->spacing[a] * (double)(1 << lv);
         for (int it = 0; it < p->iters[lv]; ++it) {
             double delta = 0.0;
             int need_delta = fine && want_uroi;
             orc_step(I0[lv], T0[lv], lx, ly, lz, kl, (const double *const *)Ip, (const double *const *)Tp,
-                     p->lambda, p->sigma_fluid, p->sigma_diff, need_delta ? uroi : NULL, p->norm_range,
+                     p->lambda, p->sigma_fluid, p->sigma_diff, hl, need_delta ? uroi : NULL, p->norm_range,
                      u, need_delta ? &delta : NULL);
             if (fine) {
                 if (hist) hist[it] = delta;

@@ -46,6 +46,11 @@ typedef struct orc_params {
     int stop_window;                  /* window of the stopping rule (iterations) */
     double norm_range;                /* intensity range that normalises delta (HU) */
     int uroi_radius[3];               /* UROI margin, semi-axes in voxels (x, y, z) */
+    double spacing[3];                /* voxel size of the finest level (e.g. mm) along x, y, z;
+                                         0 = voxel units at every level.  With a spacing,
+                                         gradients, the step of Eq.7 and the Gaussian sigmas
+                                         are in that unit, at level l the voxel size is
+                                         spacing * 2^l, and the field stays in voxels */
 } orc_params;
 
 /* Gaussian regulariser (section 2.2): sampled Gaussian of radius ceil(3 sigma),
@@ -54,6 +59,8 @@ int orc_gauss_radius(double sigma);
 int orc_gauss_weights(double sigma, double *w);
 /* Separable 3D Gaussian, x then y then z, clamped indices. out may not alias f. */
 int orc_smooth(const double *f, int nx, int ny, int nz, double sigma, double *out);
+/* The same with its own sigma (voxels) along x, y and z. */
+int orc_smooth_axes(const double *f, int nx, int ny, int nz, const double sigma[3], double *out);
 
 /* Trilinear sample of f at position (px, py, pz), position clamped to the volume. */
 double orc_sample(const double *f, int nx, int ny, int nz, double px, double py, double pz);
@@ -66,6 +73,8 @@ int orc_warp_mask(const uint8_t *m, int nx, int ny, int nz, const double *u, uin
 int orc_warp_mask_f32(const uint8_t *m, int nx, int ny, int nz, const float *u, uint8_t *out);
 /* Central differences with clamped indices: g = 3 planes. */
 int orc_gradient(const double *f, int nx, int ny, int nz, double *g);
+/* The same divided by the voxel size h[3] of each axis (h NULL: 1). */
+int orc_gradient_h(const double *f, int nx, int ny, int nz, const double *h, double *g);
 /* u_c(x) = du(x) + u(x + du(x)), per component. */
 int orc_compose(const double *u, const double *du, int nx, int ny, int nz, double *uc);
 /* R(F)(j) = (G_sigma * F)(2j); coarse dims ceil(n/2). */
@@ -90,14 +99,20 @@ double orc_eq7(double a0, double d, int k, const double *lambda, const double *a
 int orc_force(const double *wI0, const double *T0, int k, const double *const *wIp,
               const double *const *Tp, const double *lambda, int nx, int ny, int nz,
               double *du);
+/* The same with gradients in the unit of the voxel size h[3] (h NULL: voxels): Eq.7 gives a
+ * step in that unit, returned converted to voxels (component a divided by h[a]). */
+int orc_force_h(const double *wI0, const double *T0, int k, const double *const *wIp,
+                const double *const *Tp, const double *lambda, int nx, int ny, int nz,
+                const double *h, double *du);
 
 /* One iteration of the loop of Algorithm A at one level: warp, gradient, Eq.7, smooth du,
  * composite update, smooth u.  Iplus/Tplus are the k materialised modified images.
+ * h (NULL: voxel units): voxel size; gradients, the step and sigma_f, sigma_d in its unit.
  * If delta != NULL and uroi != NULL, *delta = RMS over the UROI of (T0 - I0~) / norm_range,
  * computed from u before the update.  u is updated in place. */
 int orc_step(const double *I0, const double *T0, int nx, int ny, int nz, int k,
              const double *const *Iplus, const double *const *Tplus, const double *lambda,
-             double sigma_f, double sigma_d, const uint8_t *uroi, double norm_range,
+             double sigma_f, double sigma_d, const double *h, const uint8_t *uroi, double norm_range,
              double *u, double *delta);
 
 /* Algorithm A: pyramid, demons at coarse levels, CG-DIR at the finest level.

@@ -480,7 +480,7 @@ def test_step_matches_register_single_iteration(orc):
     np.testing.assert_array_equal(u_reg, u_step)
 
 
-def _scipy_step(I0, T0, Ip, Tp, lam, sf, sd, u):
+def _scipy_step(I0, T0, Ip, Tp, lam, sf, sd, u, h=(1.0, 1.0, 1.0)):
     """One iteration of Algorithm A's loop rebuilt from library routines: linear
     map_coordinates (warp and composition), edge-padded central differences, Eq.7 in
     numpy, scipy's Gaussian filter for both smoothings."""
@@ -489,14 +489,15 @@ def _scipy_step(I0, T0, Ip, Tp, lam, sf, sd, u):
     def warp(f, v):
         return ndimage.map_coordinates(f, [z + v[2], y + v[1], x + v[0]], order=1, mode="nearest")
 
-    def grad(f):
+    def grad(f):   # per unit of h
         p = np.pad(f, 1, mode="edge")
-        return np.stack([(p[1:-1, 1:-1, 2:] - p[1:-1, 1:-1, :-2]) / 2,
-                         (p[1:-1, 2:, 1:-1] - p[1:-1, :-2, 1:-1]) / 2,
-                         (p[2:, 1:-1, 1:-1] - p[:-2, 1:-1, 1:-1]) / 2])
+        return np.stack([(p[1:-1, 1:-1, 2:] - p[1:-1, 1:-1, :-2]) / (2 * h[0]),
+                         (p[1:-1, 2:, 1:-1] - p[1:-1, :-2, 1:-1]) / (2 * h[1]),
+                         (p[2:, 1:-1, 1:-1] - p[:-2, 1:-1, 1:-1]) / (2 * h[2])])
 
-    def gauss(f, s):
-        return ndimage.gaussian_filter(f, s, mode="nearest", truncate=(np.ceil(3 * s) + 0.25) / s)
+    def gauss(f, s):   # sigma s in the unit of h: s / h voxels along each axis, radius ceil(3 sigma)
+        sv = [s / h[2], s / h[1], s / h[0]]
+        return ndimage.gaussian_filter(f, sv, mode="nearest", radius=[int(np.ceil(3 * v)) for v in sv])
 
     wI0 = warp(I0, u)
     g0 = grad(wI0)
@@ -510,7 +511,7 @@ def _scipy_step(I0, T0, Ip, Tp, lam, sf, sd, u):
         ai = (grad(wI) * n).sum(0)
         num = num + li * ai * (T - wI)
         den = den + li * ai * ai
-    du = (num / den) * n
+    du = (num / den) * n / np.asarray(h, float)[:, None, None, None]    # to voxels
     dus = np.stack([gauss(c, sf) for c in du])
     uc = dus + np.stack([warp(c, dus) for c in u])
     return np.stack([gauss(c, sd) for c in uc])
@@ -527,3 +528,56 @@ def test_step_follows_algorithm_a(orc):
     un, _ = orc.step(p.moving, p.target, Ip, Tp, lam, 1.5, 1.0, u0)
     ref = _scipy_step(p.moving.astype(float), p.target.astype(float), Ip, Tp, lam, 1.5, 1.0, u0)
     np.testing.assert_allclose(un, ref, atol=1e-9)
+
+
+def test_step_in_physical_units_follows_algorithm_a(orc):
+    """With a voxel size h the gradients are per unit of h, Eq.7's step v n is in that unit and
+    becomes h-scaled voxels, and both Gaussians take sigma in that unit (sigma / h voxels per
+    axis): the oracle's iteration == the same iteration rebuilt from library routines."""
+    p = P.head_neck_pair(dims=(40, 36, 24), amp=3.0, k=2, levels=1, iters=1)
+    u0 = P.random_smooth_field(p.dims, 2.0, 9).astype(float)
+    Ip = [orc.modified_image(p.moving, p.moving_masks[i], 1) for i in range(p.k)]
+    Tp = [orc.modified_image(p.target, p.target_masks[i], 1) for i in range(p.k)]
+    lam = [1e-3, 4e-3]
+    h = (1.97, 1.6, 2.5)
+    un, _ = orc.step(p.moving, p.target, Ip, Tp, lam, 3.0, 2.2, u0, spacing=h)
+    ref = _scipy_step(p.moving.astype(float), p.target.astype(float), Ip, Tp, lam, 3.0, 2.2, u0, h=h)
+    np.testing.assert_allclose(un, ref, atol=1e-9)
+    # a unit voxel size is the voxel-unit iteration itself
+    a, _ = orc.step(p.moving, p.target, Ip, Tp, lam, 1.5, 1.0, u0, spacing=(1.0, 1.0, 1.0))
+    b, _ = orc.step(p.moving, p.target, Ip, Tp, lam, 1.5, 1.0, u0)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_anisotropic_gaussian_and_gradient(orc):
+    rng = np.random.default_rng(12)
+    f = rng.normal(0, 1, (11, 13, 17))
+    sig = (1.3, 0.7, 2.0)                      # x, y, z voxels
+    rad = [int(np.ceil(3 * v)) for v in sig[::-1]]
+    ref = ndimage.gaussian_filter(f, sig[::-1], mode="nearest", radius=rad)
+    np.testing.assert_allclose(orc.smooth_axes(f, sig), ref, rtol=0, atol=1e-13)
+    # central differences per unit length: exact on quadratics of the physical coordinates
+    h = (1.97, 1.5, 2.5)
+    z, y, x = _grid((7, 8, 9))
+    X, Y, Z = x * h[0], y * h[1], z * h[2]
+    g = orc.gradient(X * X - 3 * Y * Y + 0.5 * Z * Z + X * Y, spacing=h)
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    np.testing.assert_allclose(g[0][inner], (2 * X + Y)[inner], atol=1e-11)
+    np.testing.assert_allclose(g[1][inner], (-6 * Y + X)[inner], atol=1e-11)
+    np.testing.assert_allclose(g[2][inner], Z[inner], atol=1e-11)
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_force_on_a_physical_ramp(orc, axis):
+    """A ramp of slope a HU per unit length along one axis, target offset by c: the gradient
+    is a, the demons step is c a / (a^2 + c^2) in length units, i.e. that over h voxels."""
+    h = (1.97, 1.97, 2.5)
+    a, c = 40.0, 25.0
+    z, y, x = _grid((9, 10, 11))
+    coord = (x, y, z)[axis] * h[axis]
+    I = a * coord
+    du = orc.force(I, I + c, [], [], [], spacing=h)
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    np.testing.assert_allclose(du[axis][inner], c * a / (a * a + c * c) / h[axis], rtol=1e-13)
+    for other in {0, 1, 2} - {axis}:
+        assert np.all(du[other][inner] == 0.0)

@@ -117,6 +117,16 @@ typedef struct cgdir_params {
     double *delta_hist;              /* optional host output: delta at each finest-level
                                         iteration (capacity iters[0]) */
     int *iters_done;                 /* optional host output: finest-level iterations run */
+    float spacing[3];                /* voxel size of the finest level along x, y, z (e.g. mm,
+                                        1.97, 1.97, 2.5 in section 2.3); {0, 0, 0} (default) =
+                                        voxel units at every level.  With a spacing the
+                                        gradients are per unit length, the step of Eq.7 is in
+                                        that unit (converted to voxels for the field),
+                                        sigma_fluid and sigma_diff are in that unit (sigma / h
+                                        voxels along each axis, radius ceil(3 sigma / h) <= 6),
+                                        and level l has voxel size spacing * 2^l.  x and y
+                                        must be equal (CGDIR_E_UNIMPL otherwise).
+                                        restrict_sigma and uroi_margin stay in voxels. */
 } cgdir_params;
 
 /* Stopping rule (section 2.2, delta = RMS intensity difference over the UROI, l = change of

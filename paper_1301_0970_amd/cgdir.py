@@ -72,6 +72,7 @@ class params(ctypes.Structure):
         ("initial_dvf_where", ctypes.c_int),
         ("delta_hist", ctypes.POINTER(ctypes.c_double)),
         ("iters_done", ctypes.POINTER(ctypes.c_int)),
+        ("spacing", ctypes.c_float * 3),
     ]
 
 
@@ -239,7 +240,9 @@ def _check(rc, what):
 
 def make_params(levels=1, iters=(100,), sigma_fluid=1.0, sigma_diff=1.0, restrict_sigma=1.0,
                 lambdas=None, signs=None, c0=1000.0, stop_mode=0, stop_eps=1e-4, stop_window=10,
-                norm_range=2500.0, uroi_margin=(5, 5, 4), contour_level_mask=1) -> params:
+                norm_range=2500.0, uroi_margin=(5, 5, 4), contour_level_mask=1, spacing=None) -> params:
+    """Library parameters; spacing = finest voxel size (x, y, z) for physical units, None for
+    voxel units (then sigma_fluid and sigma_diff are in voxels)."""
     p = params_default()
     p.levels = int(levels)
     for i, v in enumerate(iters):
@@ -261,6 +264,8 @@ def make_params(levels=1, iters=(100,), sigma_fluid=1.0, sigma_diff=1.0, restric
     for i in range(3):
         p.uroi_margin[i] = int(uroi_margin[i])
     p.contour_level_mask = int(contour_level_mask)
+    if spacing is not None:
+        p.spacing[:] = [float(v) for v in spacing]
     return p
 
 

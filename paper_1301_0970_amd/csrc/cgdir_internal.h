@@ -57,7 +57,12 @@ struct StepArgs {
     uint32_t neg;             // bit i: s_i = -1 (else +1); the modified images use s_i / 2
     float c0;                 // CT-number offset
     float inv_norm;           // 1 / norm_range
-    float w[kMaxRadius + 1];  // fluid Gaussian: w[0] centre, w[m] = weight at +-m
+    float gs[2];              // 0.5 / voxel size in-plane (x and y) and along z (0.5 in voxel
+                              // units): central differences per unit length; the step goes
+                              // back to voxels as 2 gs
+    // fluid Gaussian in-plane and along z: w[0] centre, w[m] = weight at +-m, zero past the
+    // axis' own radius (the launch's radius is the larger of the two)
+    float wxy[kMaxRadius + 1], wz[kMaxRadius + 1];
     int tz;                   // planes per block (z chunk)
     const int *stop;          // iterations after which the pair stopped (0: running)
     int iter;                 // this launch's iteration: nothing to do once *stop <= iter
@@ -69,7 +74,9 @@ struct SmoothArgs {
     const float *in[3];
     float *out[3];
     Dims d;
-    float w[kMaxRadius + 1];  // w[0] centre, w[m] = weight at +-m
+    // Gaussian in-plane and along z: w[0] centre, w[m] = weight at +-m, zero past the axis'
+    // radius
+    float wxy[kMaxRadius + 1], wz[kMaxRadius + 1];
     int tz;
     WarpArgs warp;            // where the warp goes
     const int *stop;          // iterations after which the pair stopped (0: running)
@@ -95,7 +102,7 @@ struct DeltaJob {
 // Batched launches: one launch over the tiles of n pairs.  The descriptors travel in the
 // kernel-argument segment (<= 4 KiB), so a launch holds a bounded number of pairs.
 // prefix[q] = first block of pair q, prefix[n] = total blocks.
-constexpr int kBatchStep = 16, kBatchSmooth = 20, kBatchDelta = 64;
+constexpr int kBatchStep = 14, kBatchSmooth = 18, kBatchDelta = 64;
 struct StepBatch {
     int n;
     int prefix[kBatchStep + 1];

@@ -246,9 +246,9 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
                                          uint32_t tb, int gx, int gy, int gz, float du[3], float *dout)
 {
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
-    const float g0x = 0.5f * (w[2] - w[1]);
-    const float g0y = 0.5f * (w[4] - w[3]);
-    const float g0z = 0.5f * (w[6] - w[5]);
+    const float g0x = a.gs[0] * (w[2] - w[1]);
+    const float g0y = a.gs[0] * (w[4] - w[3]);
+    const float g0z = a.gs[1] * (w[6] - w[5]);
     const float d = t0 - w[0];
     *dout = d;
     const float a02 = __builtin_fmaf(g0z, g0z, __builtin_fmaf(g0y, g0y, g0x * g0x));
@@ -274,9 +274,9 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
             const float *__restrict__ K = a.K;
             const int v = gx + nx * gy + nxy * gz;
             const float Kc = f[0] ? ldg(K, v) : 0.f;
-            const float gkx = 0.5f * ((f[2] ? ldg(K, xp + nx * gy + nxy * gz) : 0.f) - (f[1] ? ldg(K, xm + nx * gy + nxy * gz) : 0.f));
-            const float gky = 0.5f * ((f[4] ? ldg(K, gx + nx * yp + nxy * gz) : 0.f) - (f[3] ? ldg(K, gx + nx * ym + nxy * gz) : 0.f));
-            const float gkz = 0.5f * ((f[6] ? ldg(K, gx + nx * gy + nxy * zp) : 0.f) - (f[5] ? ldg(K, gx + nx * gy + nxy * zm) : 0.f));
+            const float gkx = a.gs[0] * ((f[2] ? ldg(K, xp + nx * gy + nxy * gz) : 0.f) - (f[1] ? ldg(K, xm + nx * gy + nxy * gz) : 0.f));
+            const float gky = a.gs[0] * ((f[4] ? ldg(K, gx + nx * yp + nxy * gz) : 0.f) - (f[3] ? ldg(K, gx + nx * ym + nxy * gz) : 0.f));
+            const float gkz = a.gs[1] * ((f[6] ? ldg(K, gx + nx * gy + nxy * zp) : 0.f) - (f[5] ? ldg(K, gx + nx * gy + nxy * zm) : 0.f));
             const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
             const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
             const float ai = __builtin_fmaf(hs, proj, a0);
@@ -295,23 +295,19 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
             for (int i = 0; i < a.k; ++i) {
                 const uint32_t bit = 1u << i;
                 if (kb & bit) {
-                    // K_i~ at the centre and the six clamped neighbours
-                    float Kc = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
+                    // K_i~ at the centre and the six clamped neighbours (+x, -x, +y, -y, +z, -z)
+                    float Kq[7];
 #pragma unroll 1
                     for (int q = 0; q < 7; ++q) {
                         const int px = q == 1 ? xp : (q == 2 ? xm : gx);
                         const int py = q == 3 ? yp : (q == 4 ? ym : gy);
                         const int pz = q == 5 ? zp : (q == 6 ? zm : gz);
-                        const float Kq = warp_masked(a, px, py, pz, bit);
-                        const float hK = 0.5f * Kq;
-                        if (q == 0) Kc = Kq;
-                        else if (q == 1) gkx = hK;
-                        else if (q == 2) gkx -= hK;
-                        else if (q == 3) gky = hK;
-                        else if (q == 4) gky -= hK;
-                        else if (q == 5) gkz = hK;
-                        else gkz -= hK;
+                        Kq[q] = warp_masked(a, px, py, pz, bit);
                     }
+                    const float Kc = Kq[0];
+                    const float gkx = a.gs[0] * (Kq[1] - Kq[2]);
+                    const float gky = a.gs[0] * (Kq[3] - Kq[4]);
+                    const float gkz = a.gs[1] * (Kq[5] - Kq[6]);
                     const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
                     const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
                     const float ai = __builtin_fmaf(hs, proj, a0);
@@ -329,9 +325,10 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
     num = __builtin_fmaf(lam_off * a0, d, num);
     den = __builtin_fmaf(lam_off, a02, den);
     const float vv = num * __builtin_amdgcn_rcpf(den);  // hardware reciprocal, ~1 ulp
-    du[0] = vv * nxv;
-    du[1] = vv * nyv;
-    du[2] = vv * nzv;
+    // v n is the step per unit length; in voxels along each axis it is v n / h = v n 2 gs
+    du[0] = vv * nxv * (2.f * a.gs[0]);
+    du[1] = vv * nyv * (2.f * a.gs[0]);
+    du[2] = vv * nzv * (2.f * a.gs[1]);
 }
 
 // number of tiles (blocks) of a volume for a tile of 64 x TY columns and TZ planes
@@ -393,9 +390,14 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
     const TileCoord tc = tile_of(TY, a.tz, a.d, L);
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
-    float w[R + 1];
+    // in-plane (x and y share one voxel size) and z Gaussians
+    float wx[R + 1], wz[R + 1];
 #pragma unroll
-    for (int m = 0; m <= R; ++m) w[m] = a.w[m];
+    for (int m = 0; m <= R; ++m) {
+        wx[m] = a.wxy[m];
+        wz[m] = a.wz[m];
+    }
+    const float *wy = wx;
 
     const float *__restrict__ in0 = a.in[0];
     const float *__restrict__ in1 = a.in[1];
@@ -441,18 +443,18 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
             const int r = c / kTileX, q = c - r * kTileX;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                float s = w[0] * raw[k][r][q + R];
+                float s = wx[0] * raw[k][r][q + R];
 #pragma unroll
-                for (int m = 1; m <= R; ++m) s = __builtin_fmaf(w[m], raw[k][r][q + R - m] + raw[k][r][q + R + m], s);
+                for (int m = 1; m <= R; ++m) s = __builtin_fmaf(wx[m], raw[k][r][q + R - m] + raw[k][r][q + R + m], s);
                 xs[k][r][q] = s;
             }
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            float s = w[0] * xs[k][ty + R][tx];
+            float s = wy[0] * xs[k][ty + R][tx];
 #pragma unroll
-            for (int m = 1; m <= R; ++m) s = __builtin_fmaf(w[m], xs[k][ty + R - m][tx] + xs[k][ty + R + m][tx], s);
+            for (int m = 1; m <= R; ++m) s = __builtin_fmaf(wy[m], xs[k][ty + R - m][tx] + xs[k][ty + R + m][tx], s);
             out[k] = s;
         }
     };
@@ -491,9 +493,9 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
             float s[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                float t = w[0] * ring[k][R];
+                float t = wz[0] * ring[k][R];
 #pragma unroll
-                for (int m = 1; m <= R; ++m) t = __builtin_fmaf(w[m], ring[k][R - m] + ring[k][R + m], t);
+                for (int m = 1; m <= R; ++m) t = __builtin_fmaf(wz[m], ring[k][R - m] + ring[k][R + m], t);
                 s[k] = t;
                 stg(a.out[k], v, t);
             }
@@ -551,9 +553,14 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
     const bool masked = a.F != nullptr;
     const bool metric = a.partials != nullptr;
-    float w[R + 1];
+    // in-plane (x and y share one voxel size) and z Gaussians
+    float wx[R + 1], wz[R + 1];
 #pragma unroll
-    for (int m = 0; m <= R; ++m) w[m] = a.w[m];
+    for (int m = 0; m <= R; ++m) {
+        wx[m] = a.wxy[m];
+        wz[m] = a.wz[m];
+    }
+    const float *wy = wx;
 
     // ---- I0~ / structure-bit ring (tile + R + 1 halo), clamped in-plane offsets
     int woff[NW];
@@ -739,10 +746,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                 const int r = c / kTileX, q = c - r * kTileX;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    float s = w[0] * raw[k][r][q + R];
+                    float s = wx[0] * raw[k][r][q + R];
 #pragma unroll
                     for (int m = 1; m <= R; ++m)
-                        s = __builtin_fmaf(w[m], raw[k][r][q + R - m] + raw[k][r][q + R + m], s);
+                        s = __builtin_fmaf(wx[m], raw[k][r][q + R - m] + raw[k][r][q + R + m], s);
                     xs[k][r][q] = s;
                 }
             }
@@ -759,9 +766,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                float s = w[0] * xs[k][ty + R][tx];
+                float s = wy[0] * xs[k][ty + R][tx];
 #pragma unroll
-                for (int m = 1; m <= R; ++m) s = __builtin_fmaf(w[m], xs[k][ty + R - m][tx] + xs[k][ty + R + m][tx], s);
+                for (int m = 1; m <= R; ++m) s = __builtin_fmaf(wy[m], xs[k][ty + R - m][tx] + xs[k][ty + R + m][tx], s);
                 v3[k] = s;
                 last[k] = s;
             }
@@ -782,9 +789,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             float s[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                float t = w[0] * ring[k][R];
+                float t = wz[0] * ring[k][R];
 #pragma unroll
-                for (int m = 1; m <= R; ++m) t = __builtin_fmaf(w[m], ring[k][R - m] + ring[k][R + m], t);
+                for (int m = 1; m <= R; ++m) t = __builtin_fmaf(wz[m], ring[k][R - m] + ring[k][R + m], t);
                 s[k] = t;
             }
             const Split sx = split_axis(gx, s[0], nx);

@@ -107,10 +107,10 @@ class Pool {
 
 // ------------------------------------------------------------------ derived parameters
 
-int gauss_radius(float sigma) { return sigma > 0.f ? (int)std::ceil(3.0 * (double)sigma) : 0; }
+int gauss_radius(double sigma) { return sigma > 0.0 ? (int)std::ceil(3.0 * sigma) : 0; }
 
 // sampled Gaussian of radius ceil(3 sigma), normalised to sum 1 (computed in double)
-void gauss_taps(float sigma, float *w)
+void gauss_taps(double sigma, float *w)
 {
     const int R = gauss_radius(sigma);
     for (int m = 0; m <= kMaxRadius; ++m) w[m] = 0.f;
@@ -449,9 +449,21 @@ int check_params(const cgdir_params &p, int k)
     for (int l = 0; l < p.levels; ++l)
         if (p.iters[l] < 0) return CGDIR_E_INVAL;
     if (p.contour_level_mask > 1u) return CGDIR_E_UNIMPL;
+    const bool voxel_units = p.spacing[0] == 0.f && p.spacing[1] == 0.f && p.spacing[2] == 0.f;
+    if (!voxel_units) {
+        for (int a = 0; a < 3; ++a)
+            if (!(p.spacing[a] > 0.f) || !std::isfinite(p.spacing[a])) return CGDIR_E_INVAL;
+        if (p.spacing[0] != p.spacing[1]) return CGDIR_E_UNIMPL;  // in-plane voxels are square
+    }
     const float sig[3] = {p.sigma_fluid, p.sigma_diff, p.restrict_sigma};
-    for (float s : sig)
-        if (!(s >= 0.f) || gauss_radius(s) > kMaxRadius) return CGDIR_E_INVAL;
+    for (int q = 0; q < 3; ++q) {
+        if (!(sig[q] >= 0.f) || !std::isfinite(sig[q])) return CGDIR_E_INVAL;
+        // the finest level has the most voxels per unit length: the largest radius
+        for (int a = 0; a < 3; ++a) {
+            const double h = (voxel_units || q == 2) ? 1.0 : (double)p.spacing[a];
+            if (gauss_radius((double)sig[q] / h) > kMaxRadius) return CGDIR_E_INVAL;
+        }
+    }
     for (int i = 0; i < k; ++i) {
         if (!(p.lambda[i] >= 0.f) || !std::isfinite(p.lambda[i])) return CGDIR_E_INVAL;
         if (p.sign[i] < -1 || p.sign[i] > 1) return CGDIR_E_INVAL;
@@ -516,8 +528,12 @@ struct Job {
     bool delta_on = false;
     float lam[kMaxStructs] = {}, hs[kMaxStructs] = {};
     int sign[kMaxStructs] = {};
-    float wf[kMaxRadius + 1], wd[kMaxRadius + 1], wr[kMaxRadius + 1];
-    int Rf = 0, Rd = 0, Rr = 0;
+    // Gaussians per level and axis (sigma / voxel size of the level, or sigma in voxels), and
+    // each level's launch radius (the largest of the three axes)
+    float wf[CGDIR_MAX_LEVELS][3][kMaxRadius + 1], wd[CGDIR_MAX_LEVELS][3][kMaxRadius + 1];
+    float wr[kMaxRadius + 1];
+    int Rf[CGDIR_MAX_LEVELS] = {}, Rd[CGDIR_MAX_LEVELS] = {}, Rr = 0;
+    float gs[CGDIR_MAX_LEVELS][3];   // 0.5 / voxel size per level and axis
 
     std::vector<void *> allocs;
     const float *I0[CGDIR_MAX_LEVELS] = {}, *T0[CGDIR_MAX_LEVELS] = {};
@@ -567,11 +583,21 @@ struct Job {
             lam[i] = r.params.lambda[i];
             sign[i] = r.params.sign[i];
         }
-        gauss_taps(r.params.sigma_fluid, wf);
-        gauss_taps(r.params.sigma_diff, wd);
+        const bool voxel_units =
+            r.params.spacing[0] == 0.f && r.params.spacing[1] == 0.f && r.params.spacing[2] == 0.f;
+        for (int l = 0; l < L; ++l) {
+            Rf[l] = Rd[l] = 0;
+            for (int a = 0; a < 3; ++a) {
+                const double h = voxel_units ? 1.0 : (double)r.params.spacing[a] * (double)(1 << l);
+                const double sf = (double)r.params.sigma_fluid / h, sd = (double)r.params.sigma_diff / h;
+                gauss_taps(sf, wf[l][a]);
+                gauss_taps(sd, wd[l][a]);
+                Rf[l] = std::max(Rf[l], gauss_radius(sf));
+                Rd[l] = std::max(Rd[l], gauss_radius(sd));
+                gs[l][a] = (float)(0.5 / h);
+            }
+        }
         gauss_taps(r.params.restrict_sigma, wr);
-        Rf = gauss_radius(r.params.sigma_fluid);
-        Rd = gauss_radius(r.params.sigma_diff);
         Rr = gauss_radius(r.params.restrict_sigma);
         level = L - 1;
         iter = 0;
@@ -831,7 +857,12 @@ struct Job {
         }
         sa.c0 = req.params.intensity_offset;
         sa.inv_norm = 1.0f / req.params.norm_range;
-        for (int m = 0; m <= kMaxRadius; ++m) sa.w[m] = wf[m];
+        for (int m = 0; m <= kMaxRadius; ++m) {
+            sa.wxy[m] = wf[level][0][m];
+            sa.wz[m] = wf[level][2][m];
+        }
+        sa.gs[0] = gs[level][0];
+        sa.gs[1] = gs[level][2];
         sa.tz = ctx->tune.step_tz;
         sa.stop = delta_on ? stop_dev : nullptr;
         sa.iter = iter;
@@ -862,7 +893,10 @@ struct Job {
         }
         sb.d = level_dims(d0, level);
         sb.tz = ctx->tune.smooth_tz;
-        for (int m = 0; m <= kMaxRadius; ++m) sb.w[m] = wd[m];
+        for (int m = 0; m <= kMaxRadius; ++m) {
+            sb.wxy[m] = wd[level][0][m];
+            sb.wz[m] = wd[level][2][m];
+        }
         sb.warp = warp_args();
         sb.stop = delta_on ? stop_dev : nullptr;
         sb.iter = iter;
@@ -999,8 +1033,8 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
 
     std::map<int, std::vector<int>> by_rf, by_rd;
     for (int i : act) {
-        by_rf[jobs[i]->Rf].push_back(i);
-        by_rd[jobs[i]->Rd].push_back(i);
+        by_rf[jobs[i]->Rf[jobs[i]->level]].push_back(i);
+        by_rd[jobs[i]->Rd[jobs[i]->level]].push_back(i);
     }
     for (auto &g : by_rf) {
         const std::vector<int> &v = g.second;

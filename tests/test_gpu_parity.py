@@ -105,6 +105,54 @@ def test_step_with_different_sigmas(ctx, orc):
     assert np.abs(ug - uo).max() <= STEP_TOL
 
 
+@pytest.mark.parametrize("spacing,sigma", [((1.97, 1.97, 2.5), 1.97), ((1.2, 1.2, 3.0), 2.0)],
+                         ids=["1.97x1.97x2.5 mm sigma 1.97", "1.2x1.2x3 mm sigma 2"])
+def test_step_in_physical_units(ctx, orc, spacing, sigma):
+    """Anisotropic voxels: gradients per mm, the step in mm converted to voxels, Gaussians of
+    sigma mm (in the second case radius 5 in-plane and 2 or 3 along z: the z taps are
+    zero-padded to the launch radius)."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(110, 84, 40), amp=4.0, k=3)
+    u0 = P.random_smooth_field(pair.dims, 3.0, 17)
+    lam, sg = [1e-3, 2e-3, 3e-3], [1, -1, 1]
+    prm = cgdir.make_params(levels=1, iters=(1,), sigma_fluid=sigma, sigma_diff=0.8 * sigma, lambdas=lam,
+                            signs=sg, spacing=spacing)
+    say("step in mm %s sigma %.2f" % (spacing, sigma))
+    ug = gpu_register(ctx, pair, prm, initial=u0)
+    Ip = [orc.modified_image(pair.moving, pair.moving_masks[i], sg[i]) for i in range(3)]
+    Tp = [orc.modified_image(pair.target, pair.target_masks[i], sg[i]) for i in range(3)]
+    h = [float(np.float32(v)) for v in spacing]
+    uo, _ = orc.step(pair.moving, pair.target, Ip, Tp, lam, float(np.float32(sigma)),
+                     float(np.float32(0.8 * sigma)), u0.astype(np.float64), spacing=h)
+    err = np.abs(ug - uo).max()
+    say("  max |du| %.3g  max err %.3g" % (np.abs(uo - u0).max(), err))
+    assert err <= STEP_TOL
+
+
+def test_pyramid_in_physical_units(ctx, orc):
+    """Two levels with voxel size 1.97 x 1.97 x 2.5 mm (3.94 x 3.94 x 5 at the coarse level)."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(90, 76, 40), amp=4.0, k=3, levels=2, iters=25)
+    h = (1.97, 1.97, 2.5)
+    say("pyramid in mm")
+    ug = gpu_register(ctx, pair, cgdir.params_for_pair(pair, sigma_fluid=2.5, sigma_diff=2.5, spacing=h))
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, sigma_fluid=float(np.float32(2.5)),
+                                           sigma_diff=float(np.float32(2.5)),
+                                           spacing=[float(np.float32(v)) for v in h]))
+    err = np.abs(ug - uo).max()
+    rms = np.sqrt(((orc.warp(pair.moving, ug) - orc.warp(pair.moving, uo)) ** 2).mean())
+    say("  final max err %.3g voxel, warped rms %.3g HU" % (err, rms))
+    assert err <= FINAL_TOL and rms <= WARP_RMS_TOL
+    with pytest.raises(cgdir.CgdirError) as e:   # in-plane voxels must be square
+        gpu_register(ctx, pair, cgdir.params_for_pair(pair, spacing=(1.0, 1.5, 2.0)))
+    assert e.value.code == cgdir.E_UNIMPL
+    for bad in ((1.0, 1.0, -2.0), (0.2, 0.2, 0.2)):   # negative; sigma 1 mm = 5 voxels -> radius 15
+        with pytest.raises(cgdir.CgdirError) as e:
+            gpu_register(ctx, pair, cgdir.params_for_pair(pair, spacing=bad))
+        assert e.value.code == cgdir.E_INVAL, bad
+
+
 def test_full_run_plain(ctx, orc):
     """Config 1 in full: 64x64x32, 1 level x 100 iterations, k = 1."""
     from paper_1301_0970_amd import cgdir

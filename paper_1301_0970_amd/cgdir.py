@@ -122,6 +122,10 @@ class eval_result(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libcgdir.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one the library binds
+    # to.  Loaded the other way round, the process ends up with two HIP runtimes and the
+    # library's cannot open the device that torch's already holds.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     lib.cgdir_params_default.argtypes = [P(params)]

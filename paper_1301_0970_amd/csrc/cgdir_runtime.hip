@@ -1139,23 +1139,23 @@ void scheduler(cgdir_ctx *c)
     std::vector<cgdir_ctx::Request *> active;
     std::deque<hipEvent_t> ticks;
     for (;;) {
-        {
-            std::unique_lock<std::mutex> lk(c->mu);
-            // admission, in arrival order
-            while (!c->queue.empty() && (int)active.size() < c->max_slots) {
-                auto it = c->reqs.find(c->queue.front());
-                if (it == c->reqs.end() || it->second->state != CGDIR_QUEUED) {
+        // admission, in arrival order.  The request leaves the queue under mu; its set-up
+        // launches run after mu is released, so that poll, submit and cancel never wait for
+        // the launch lock (a blocking registration may hold it for a long time).
+        for (;;) {
+            cgdir_ctx::Request *r = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(c->mu);
+                while (!c->queue.empty()) {
+                    auto it = c->reqs.find(c->queue.front());
+                    if (it != c->reqs.end() && it->second->state == CGDIR_QUEUED) break;
                     c->queue.pop_front();
-                    continue;
                 }
-                cgdir_ctx::Request *r = it->second.get();
-                int rc = r->job.allocate();
+                if (c->queue.empty() || (int)active.size() >= c->max_slots) break;
+                r = c->reqs.find(c->queue.front())->second.get();
+                const int rc = r->job.allocate();
                 if (rc == CGDIR_E_NOMEM) break;  // the head of the queue waits for memory
                 c->queue.pop_front();
-                if (rc == CGDIR_OK) {
-                    std::lock_guard<std::mutex> lg(c->launch_mu);
-                    rc = r->job.setup();
-                }
                 if (rc != CGDIR_OK) {
                     finish_request(r, rc);
                     c->cv.notify_all();
@@ -1163,13 +1163,26 @@ void scheduler(cgdir_ctx *c)
                 }
                 r->state = CGDIR_RUNNING;
                 r->t_admit = now_ns();
-                active.push_back(r);
             }
-            if (active.empty()) {
-                if (c->stopping && c->queue.empty()) break;
-                c->cv.wait_for(lk, std::chrono::milliseconds(20));
+            int rc;
+            {
+                std::lock_guard<std::mutex> lg(c->launch_mu);
+                rc = r->job.setup();
+            }
+            if (rc != CGDIR_OK) {
+                hipStreamSynchronize(c->stream);  // set-up work in flight may still use its memory
+                std::lock_guard<std::mutex> lk(c->mu);
+                finish_request(r, rc);
+                c->cv.notify_all();
                 continue;
             }
+            active.push_back(r);
+        }
+        if (active.empty()) {
+            std::unique_lock<std::mutex> lk(c->mu);
+            if (c->stopping && c->queue.empty()) break;
+            c->cv.wait_for(lk, std::chrono::milliseconds(20));  // new work, or memory for the head
+            continue;
         }
         // one tick: every admitted request advances one iteration
         {

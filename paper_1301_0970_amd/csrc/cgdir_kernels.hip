@@ -726,10 +726,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                     }
                     float du[3], d;
                     force_at(a, w7, f7, pt[j], ptb[j], cx, cy, pc, du, &d);
-                    const int r = c / WD, q = c - r * WD;
-                    raw[0][r][q] = du[0];
-                    raw[1][r][q] = du[1];
-                    raw[2][r][q] = du[2];
+                    (&raw[0][0][0])[c] = du[0];  // cell c is row c / WD, column c % WD
+                    (&raw[1][0][0])[c] = du[1];
+                    (&raw[2][0][0])[c] = du[2];
                     if (metric && dqi[j] >= 0) {
                         const float e = d * a.inv_norm;
                         (&dq[0][0])[dqi[j]] = pur[j] ? e * e : 0.f;
@@ -797,23 +796,32 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             const Split sx = split_axis(gx, s[0], nx);
             const Split sy = split_axis(gy, s[1], ny);
             const Split sz = split_axis(z, s[2], nz);
-            const bool near = sx.i0 >= gx - 1 && sx.i1 <= gx + 1 && sy.i0 >= gy - 1 && sy.i1 <= gy + 1 &&
-                              sz.i0 >= z - 1 && sz.i1 <= z + 1;
+            // corner offsets from the voxel, -1, 0 or +1 when all corners lie in the ring
+            const int ox0 = sx.i0 - gx, ox1 = sx.i1 - gx, oy0 = sy.i0 - gy, oy1 = sy.i1 - gy;
+            const int oz0 = sz.i0 - z, oz1 = sz.i1 - z;
+            const bool near = ox0 >= -1 && ox1 <= 1 && oy0 >= -1 && oy1 <= 1 && oz0 >= -1 && oz1 <= 1;
             if (near) {  // all corners in the staged planes
-                const int cx0 = sx.i0 - (x0 - 1), cx1 = sx.i1 - (x0 - 1);
-                const int ry0 = (sy.i0 - (y0 - 1)) * UW, ry1 = (sy.i1 - (y0 - 1)) * UW;
-                const int sl0 = (sz.i0 - z0 + 1) % 3, sl1 = (sz.i1 - z0 + 1) % 3;
+                // ring cells: the plane's slot base (uniform), the row and the column
+                const int zs_m = ((z - z0) % 3) * UCELLS, zs_0 = ((z - z0 + 1) % 3) * UCELLS;
+                const int zs_p = ((z - z0 + 2) % 3) * UCELLS;
+                const int b0 = oz0 < 0 ? zs_m : (oz0 == 0 ? zs_0 : zs_p);
+                const int b1 = oz1 < 0 ? zs_m : (oz1 == 0 ? zs_0 : zs_p);
+                const int own_c = (ty + 1) * UW + tx + 1;
+                const int r0 = own_c + (oy0 < 0 ? -UW : (oy0 > 0 ? UW : 0));
+                const int r1 = own_c + (oy1 < 0 ? -UW : (oy1 > 0 ? UW : 0));
+                const int i00 = b0 + r0, i01 = b0 + r1, i10 = b1 + r0, i11 = b1 + r1;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
+                    const float *U = &Us[k][0][0];
                     float f[8];
-                    f[0] = Us[k][sl0][ry0 + cx0];
-                    f[1] = Us[k][sl0][ry0 + cx1];
-                    f[2] = Us[k][sl0][ry1 + cx0];
-                    f[3] = Us[k][sl0][ry1 + cx1];
-                    f[4] = Us[k][sl1][ry0 + cx0];
-                    f[5] = Us[k][sl1][ry0 + cx1];
-                    f[6] = Us[k][sl1][ry1 + cx0];
-                    f[7] = Us[k][sl1][ry1 + cx1];
+                    f[0] = U[i00 + ox0];
+                    f[1] = U[i00 + ox1];
+                    f[2] = U[i01 + ox0];
+                    f[3] = U[i01 + ox1];
+                    f[4] = U[i10 + ox0];
+                    f[5] = U[i10 + ox1];
+                    f[6] = U[i11 + ox0];
+                    f[7] = U[i11 + ox1];
                     stg(a.uc[k], v, s[k] + lerp8(f, sx.t, sy.t, sz.t));
                 }
             } else {

@@ -195,9 +195,11 @@ const char *kKernelNames[K_COUNT] = {"step", "smooth", "delta", "restrict", "pro
 struct TileCfg {
     int ty, tz;
 };
-const TileCfg kStepCands[] = {{8, 32}, {8, 16}, {8, 64}, {8, 128}, {16, 16}, {16, 32}, {16, 64}, {16, 128}, {4, 32}, {4, 128}, {8, 8}, {4, 8}, {4, 16}};
+// (the small z chunks give coarse pyramid levels enough blocks to fill 256 CUs)
+const TileCfg kStepCands[] = {{8, 32}, {8, 16}, {8, 64}, {8, 128}, {16, 16}, {16, 32}, {16, 64}, {16, 128},
+                              {4, 32}, {4, 128}, {8, 8}, {4, 8}, {4, 16}, {8, 4}, {4, 4}};
 const TileCfg kSmoothCands[] = {{8, 32}, {8, 8}, {8, 16}, {8, 64}, {8, 128}, {16, 16}, {16, 32}, {16, 64},
-                                {16, 128}, {4, 16}, {4, 64}};
+                                {16, 128}, {4, 16}, {4, 64}, {4, 8}, {8, 4}, {4, 4}};
 
 class Tuner {
   public:

@@ -207,3 +207,49 @@ def test_early_stop_on_the_device_alone_batched_and_served():
         assert [d.value for d in done] == ns
         for (u, _, _), o in zip(alone, outs):
             np.testing.assert_array_equal(u.cpu().numpy(), o.cpu().numpy())
+
+
+def test_concurrent_submitters_and_a_blocking_registration():
+    """Four threads submit and poll at once while the main thread runs blocking registrations
+    on the same context: every result equals the pair's result alone, and poll answers while a
+    blocking registration holds the launch lock."""
+    import threading
+
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pairs = _pairs()
+    items = _items(pairs)
+    prms = [cgdir.params_for_pair(p) for p in pairs]
+    with cgdir.Context(4 << 30, max_slots=3) as ctx:
+        say("concurrent: alone")
+        alone = [ctx.register(*it, prm=pr).cpu().numpy() for it, pr in zip(items, prms)]
+        results, errors = {}, []
+
+        def worker(w):
+            try:
+                outs, tickets = [], []
+                for j in range(len(pairs)):
+                    q = (j + w) % len(pairs)
+                    o = torch.empty((3,) + tuple(pairs[q].target.shape), device="cuda")
+                    tickets.append((q, ctx.submit(*items[q], prms[q], o), o))
+                for q, t, o in tickets:
+                    while ctx.poll(t).state not in (cgdir.DONE, cgdir.FAILED, cgdir.CANCELLED):
+                        time.sleep(0.001)
+                    assert ctx.wait(t) == cgdir.OK
+                    results[(w, q)] = o.cpu().numpy()
+            except Exception as e:  # noqa: BLE001 - reported below
+                errors.append(repr(e))
+
+        say("concurrent: 4 submitters + blocking registrations")
+        threads = [threading.Thread(target=worker, args=(w,)) for w in range(4)]
+        for th in threads:
+            th.start()
+        blocking = [ctx.register(*items[q], prm=prms[q]).cpu().numpy() for q in (2, 0)]
+        for th in threads:
+            th.join(120)
+        assert not errors, errors
+        assert len(results) == 4 * len(pairs)
+        for (w, q), o in results.items():
+            np.testing.assert_array_equal(o, alone[q])
+        np.testing.assert_array_equal(blocking[0], alone[2])
+        np.testing.assert_array_equal(blocking[1], alone[0])

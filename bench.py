@@ -220,6 +220,37 @@ def evaluated(cgdir, torch, pair, pool):
     return out
 
 
+def warm_start(cgdir, torch, pair, pool, iters=30):
+    """Re-registration from an existing field (finest level only, no coarse demons) against
+    the full pyramid: latency and the resulting overlap (device evaluation)."""
+    dev = torch.device("cuda")
+    t = torch.from_numpy(pair.target).to(dev)
+    m = torch.from_numpy(pair.moving).to(dev)
+    tm = torch.from_numpy(pair.target_masks).to(dev)
+    mm = torch.from_numpy(pair.moving_masks).to(dev)
+    out = {}
+    with cgdir.Context(pool) as ctx:
+        full = cgdir.params_for_pair(pair)
+        ctx.register(t, m, tm, mm, full)                           # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = ctx.register(t, m, tm, mm, full)
+        torch.cuda.synchronize()
+        out["full_ms"] = (time.perf_counter() - t0) * 1e3
+        out["full_dsc_mean"] = float(np.mean([s["dsc"] for s in ctx.evaluate(t, m, tm, mm, u)["structures"]]))
+        # the previous field as the start of a finest-level-only run (e.g. the next fraction)
+        warm = cgdir.params_for_pair(pair, levels=1, iters=(iters,))
+        ctx.register(t, m, tm, mm, warm, initial=u)                # warm-up of the tile shapes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uw = ctx.register(t, m, tm, mm, warm, initial=u)
+        torch.cuda.synchronize()
+        out["warm_ms"] = (time.perf_counter() - t0) * 1e3
+        out["warm_iters"] = iters
+        out["warm_dsc_mean"] = float(np.mean([s["dsc"] for s in ctx.evaluate(t, m, tm, mm, uw)["structures"]]))
+    return out
+
+
 def batched(cgdir, P, torch, n_pairs):
     """The uneven batch (sizes and structure counts drawn per pair): all pairs in one
     cgdir_register_batch call vs the same pairs registered one at a time."""
@@ -265,6 +296,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0, metavar="PAIRS",
                     help="also run the uneven batched workload with this many pairs (32 in full)")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--warm-start", action="store_true",
+                    help="also time a finest-level re-registration started from the full result")
     ap.add_argument("--evaluate", action="store_true",
                     help="also evaluate (section 2.3 metrics) CG-DIR against plain demons on the workload")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
@@ -364,6 +397,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(pair)
+    if args.warm_start:
+        log("warm start")
+        result["warm_start"] = warm_start(cgdir, torch, pair, pool + (1 << 30))
     if args.evaluate:
         log("evaluation")
         result["evaluation"] = evaluated(cgdir, torch, pair, pool + (1 << 30))

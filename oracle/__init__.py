@@ -213,6 +213,17 @@ def restrict(f, sigma: float = 1.0) -> np.ndarray:
     return out
 
 
+def decimate_masks(masks) -> np.ndarray:
+    """Masks (k, nz, ny, nx) at the next coarser pyramid level (contour terms below the
+    finest level): inside where the fine voxel at the even indices is inside."""
+    masks = _u8(masks)
+    k = masks.shape[0]
+    nx, ny, nz = _dims(masks)
+    out = np.empty((k, (nz + 1) // 2, (ny + 1) // 2, (nx + 1) // 2), np.uint8)
+    _check(lib().orc_decimate_masks(_ptr(masks), k, nx, ny, nz, _ptr(out)), "decimate_masks")
+    return out
+
+
 def prolong(uc, fine_dims) -> np.ndarray:
     uc = _f64(uc)
     fnx, fny, fnz = fine_dims

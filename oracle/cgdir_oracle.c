@@ -351,6 +351,21 @@ int orc_restrict(const double *f, int nx, int ny, int nz, double sigma, double *
     return 0;
 }
 
+int orc_decimate_masks(const uint8_t *m, int k, int nx, int ny, int nz, uint8_t *out)
+{
+    if (bad_dims(nx, ny, nz) || k < 0) return -1;
+    size_t n = (size_t)nx * ny * nz;
+    int cx = (nx + 1) / 2, cy = (ny + 1) / 2, cz = (nz + 1) / 2;
+    size_t cn = (size_t)cx * cy * cz;
+    for (int s = 0; s < k; ++s)
+        for (int l = 0; l < cz; ++l)
+            for (int j = 0; j < cy; ++j)
+                for (int i = 0; i < cx; ++i)
+                    out[s * cn + (size_t)i + (size_t)cx * ((size_t)j + (size_t)cy * l)] =
+                        m[s * n + IDX(2 * i, 2 * j, 2 * l)] != 0;
+    return 0;
+}
+
 int orc_prolong(const double *uc, int cnx, int cny, int cnz, int fnx, int fny, int fnz, double *uf)
 {
     if (bad_dims(cnx, cny, cnz) || bad_dims(fnx, fny, fnz)) return -1;
@@ -499,7 +514,7 @@ int orc_register(const double *target, const double *moving, int nx, int ny, int
     if (bad_dims(nx, ny, nz) || !p || k < 0 || k > ORC_MAX_STRUCTS) return -1;
     int L = p->levels;
     if (L < 1 || L > ORC_MAX_LEVELS) return -1;
-    if (p->contour_level_mask & ~1u) return -1;
+    if (p->contour_level_mask >> L) return -1;
     if (initial_u && L != 1) return -1;
     for (int lv = 0; lv < L; ++lv)
         if (p->iters[lv] < 0) return -1;
@@ -520,6 +535,20 @@ int orc_register(const double *target, const double *moving, int nx, int ny, int
         T0[lv] = (double *)malloc(sizeof(double) * nl);
         orc_restrict(I0[lv - 1], dims[lv - 1][0], dims[lv - 1][1], dims[lv - 1][2], p->restrict_sigma, I0[lv]);
         orc_restrict(T0[lv - 1], dims[lv - 1][0], dims[lv - 1][1], dims[lv - 1][2], p->restrict_sigma, T0[lv]);
+    }
+    /* the structure masks of every level that has contour terms (and of the levels between) */
+    const uint8_t *TM[ORC_MAX_LEVELS] = {tmasks}, *MM[ORC_MAX_LEVELS] = {mmasks};
+    uint8_t *own_masks[2 * ORC_MAX_LEVELS] = {0};
+    int top = 0;
+    for (int lv = 1; lv < L; ++lv)
+        if ((p->contour_level_mask >> lv) & 1u) top = lv;
+    for (int lv = 1; lv <= top && k > 0; ++lv) {
+        size_t nl = (size_t)dims[lv][0] * dims[lv][1] * dims[lv][2];
+        uint8_t *t = (uint8_t *)malloc((size_t)k * nl), *m = (uint8_t *)malloc((size_t)k * nl);
+        orc_decimate_masks(TM[lv - 1], k, dims[lv - 1][0], dims[lv - 1][1], dims[lv - 1][2], t);
+        orc_decimate_masks(MM[lv - 1], k, dims[lv - 1][0], dims[lv - 1][1], dims[lv - 1][2], m);
+        TM[lv] = own_masks[2 * lv] = t;
+        MM[lv] = own_masks[2 * lv + 1] = m;
     }
 
     /* u0 := 0 at the coarsest level (or the given initial field) */
@@ -560,8 +589,8 @@ int orc_register(const double *target, const double *moving, int nx, int ny, int
             for (int s = 0; s < kl; ++s) {
                 Ip[s] = (double *)malloc(sizeof(double) * nl);
                 Tp[s] = (double *)malloc(sizeof(double) * nl);
-                orc_modified_image(I0[lv], mmasks + (size_t)s * nl, sign[s], p->c0, nl, Ip[s]);
-                orc_modified_image(T0[lv], tmasks + (size_t)s * nl, sign[s], p->c0, nl, Tp[s]);
+                orc_modified_image(I0[lv], MM[lv] + (size_t)s * nl, sign[s], p->c0, nl, Ip[s]);
+                orc_modified_image(T0[lv], TM[lv] + (size_t)s * nl, sign[s], p->c0, nl, Tp[s]);
             }
         }
         int fine = (lv == 0);
@@ -598,5 +627,6 @@ int orc_register(const double *target, const double *moving, int nx, int ny, int
     free(uroi);
     if (hist != delta_hist) free(hist);
     for (int lv = 0; lv < L; ++lv) { free(I0[lv]); free(T0[lv]); }
+    for (int q = 0; q < 2 * ORC_MAX_LEVELS; ++q) free(own_masks[q]);
     return 0;
 }

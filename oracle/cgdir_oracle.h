@@ -15,8 +15,9 @@
  *
  * Parity unpinned (no number in the paper tests them; the oracle and the HIP path
  * implement the same written reading): the CT-number offset c0 of the modified
- * images, the pyramid filter, the UROI structuring element, the stopping rule and
- * every border convention (index clamping).
+ * images, the pyramid filter, the UROI structuring element, the stopping rule,
+ * every border convention (index clamping) and the choice of the masks at coarse levels
+ * (the paper's Algorithm A uses none there).
  */
 #ifndef CGDIR_ORACLE_H
 #define CGDIR_ORACLE_H
@@ -34,7 +35,9 @@ extern "C" {
 typedef struct orc_params {
     int levels;                       /* pyramid levels, >= 1 */
     int iters[ORC_MAX_LEVELS];        /* iterations per level, index 0 = finest */
-    unsigned contour_level_mask;      /* bit l: contour terms active at level l (only bit 0 supported) */
+    unsigned contour_level_mask;      /* bit l: contour terms active at level l (l < levels);
+                                         at a coarse level the masks are those of
+                                         orc_decimate_masks applied l times */
     double sigma_fluid;               /* Gaussian sigma applied to du (voxels) */
     double sigma_diff;                /* Gaussian sigma applied to u (voxels) */
     double restrict_sigma;            /* Gaussian sigma of the pyramid restriction */
@@ -79,6 +82,11 @@ int orc_gradient_h(const double *f, int nx, int ny, int nz, const double *h, dou
 int orc_compose(const double *u, const double *du, int nx, int ny, int nz, double *uc);
 /* R(F)(j) = (G_sigma * F)(2j); coarse dims ceil(n/2). */
 int orc_restrict(const double *f, int nx, int ny, int nz, double sigma, double *out);
+/* Structure masks at the next coarser level, where Algorithm A's variant with contour terms
+ * below the finest level needs them: a coarse voxel is inside when the fine voxel it stands
+ * for (even indices, as the restriction keeps) is inside.  m, out: k masks; coarse dims
+ * ceil(n/2). */
+int orc_decimate_masks(const uint8_t *m, int k, int nx, int ny, int nz, uint8_t *out);
 /* u_f(x) = 2 u_c(x / 2) trilinear; coarse dims must be ceil(fine/2). */
 int orc_prolong(const double *uc, int cnx, int cny, int cnz, int fnx, int fny, int fnz,
                 double *uf);

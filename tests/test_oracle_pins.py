@@ -327,6 +327,29 @@ def test_prolong_constants_and_affine(orc):
     np.testing.assert_allclose(uf[0][inner], expect[inner], atol=1e-12)
 
 
+def test_decimate_masks_closed_form(orc):
+    """Masks at a coarser level (contour terms below the finest level): a fine box
+    [a, b] (inclusive, per axis) becomes the coarse box [ceil(a/2), floor(b/2)], and after two
+    levels [ceil(a/4), floor(b/4)]; any nonzero fine value counts as inside; dims ceil(n/2)."""
+    shape = (13, 19, 23)                       # (nz, ny, nx)
+    lo, hi = (3, 5, 2), (10, 12, 19)           # z, y, x bounds of the box
+    m = np.zeros((2,) + shape, np.uint8)
+    m[0][lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1] = 7
+    m[1][12, 18, 22] = 255                     # the last voxel, all indices even
+    m[1][8, 16, 20] = 1                        # indices divisible by 4
+    m[1][11, 0, 0] = 1                         # odd z index: dropped
+    c1 = orc.decimate_masks(m)
+    c2 = orc.decimate_masks(c1)
+    assert c1.shape == (2, 7, 10, 12) and c2.shape == (2, 4, 5, 6)
+    for c, f in ((c1, 2), (c2, 4)):
+        box = np.zeros(c.shape[1:], np.uint8)
+        box[-(-lo[0] // f):hi[0] // f + 1, -(-lo[1] // f):hi[1] // f + 1, -(-lo[2] // f):hi[2] // f + 1] = 1
+        np.testing.assert_array_equal(c[0], box)
+    assert sorted(map(tuple, np.argwhere(c1[1]))) == [(4, 8, 10), (6, 9, 11)]
+    assert sorted(map(tuple, np.argwhere(c2[1]))) == [(2, 4, 5)]
+    assert c1.max() == 1
+
+
 # ------------------------------------------------------------------ UROI and signs
 
 def test_uroi_matches_binary_dilation(orc):
@@ -371,9 +394,10 @@ def _small_pair(**kw):
 def test_identity_gives_zero_field(orc):
     """P4: identical images and masks -> du == 0 everywhere, u stays exactly 0."""
     p = _small_pair()
-    prm = orc.params_for(p, levels=2, iters=(5, 5))
-    u, _, _ = orc.register(p.target, p.target, p.target_masks, p.target_masks, prm)
-    assert np.all(u == 0.0)
+    for mask in (1, 3):   # contour terms at the finest level only, and at both levels
+        prm = orc.params_for(p, levels=2, iters=(5, 5), contour_level_mask=mask)
+        u, _, _ = orc.register(p.target, p.target, p.target_masks, p.target_masks, prm)
+        assert np.all(u == 0.0)
 
 
 def test_contour_term_vanishes_when_masks_agree(orc):
@@ -528,6 +552,38 @@ def test_step_follows_algorithm_a(orc):
     un, _ = orc.step(p.moving, p.target, Ip, Tp, lam, 1.5, 1.0, u0)
     ref = _scipy_step(p.moving.astype(float), p.target.astype(float), Ip, Tp, lam, 1.5, 1.0, u0)
     np.testing.assert_allclose(un, ref, atol=1e-9)
+
+
+def test_contour_terms_at_a_coarse_level_follow_algorithm_a(orc):
+    """Contour terms at the coarse level of a two-level pyramid (the finest level runs no
+    iteration): the result equals Algorithm A's loop rebuilt from library routines at that
+    level, on images restricted by scipy's Gaussian then every other voxel and on masks
+    taken at the even voxels, then prolongated as 2 u(x / 2) by scipy's linear interpolation."""
+    p = P.head_neck_pair(dims=(38, 34, 22), amp=3.0, k=2, levels=2, iters=1)
+    lam = [2e-3, 5e-3]
+    prm = orc.params_for(p, levels=2, iters=(0, 3), lambdas=lam, contour_level_mask=2)
+    u, _, _ = orc.register(p.target, p.moving, p.target_masks, p.moving_masks, prm)
+
+    def down(f):
+        return ndimage.gaussian_filter(f.astype(float), 1.0, mode="nearest", truncate=3.25)[::2, ::2, ::2]
+    I0, T0 = down(p.moving), down(p.target)
+    mm, tm = p.moving_masks[:, ::2, ::2, ::2], p.target_masks[:, ::2, ::2, ::2]
+    Ip = [orc.modified_image(I0, mm[i], p.signs[i]) for i in range(p.k)]
+    Tp = [orc.modified_image(T0, tm[i], p.signs[i]) for i in range(p.k)]
+    uc = np.zeros((3,) + I0.shape)
+    for _ in range(3):
+        uc = _scipy_step(I0, T0, Ip, Tp, lam, p.sigma, p.sigma, uc)
+    z, y, x = _grid(p.target.shape)
+    ref = np.stack([2.0 * ndimage.map_coordinates(c, [z / 2, y / 2, x / 2], order=1, mode="nearest")
+                    for c in uc])
+    np.testing.assert_allclose(u, ref, atol=1e-9)
+    # the same run without contour terms differs, and contour bits beyond the levels are refused
+    u0, _, _ = orc.register(p.target, p.moving, p.target_masks, p.moving_masks,
+                            orc.params_for(p, levels=2, iters=(0, 3), lambdas=lam, contour_level_mask=0))
+    assert np.abs(u - u0).max() > 1e-3
+    with pytest.raises(ValueError):
+        orc.register(p.target, p.moving, p.target_masks, p.moving_masks,
+                     orc.params_for(p, levels=2, iters=(0, 3), contour_level_mask=4))
 
 
 def test_step_in_physical_units_follows_algorithm_a(orc):

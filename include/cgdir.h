@@ -93,7 +93,10 @@ typedef struct cgdir_params {
     int levels;                      /* pyramid levels; default 1.  The paper uses 2 (section 2.2) */
     int iters[CGDIR_MAX_LEVELS];     /* iterations per level, index 0 = finest; default 100 */
     unsigned contour_level_mask;     /* bit l: contour terms at level l; default 1 (finest only,
-                                        Algorithm A); only bit 0 is supported */
+                                        as in Algorithm A).  At a coarse level l the structure
+                                        masks are those of the finest voxels at indices
+                                        2^l (i, j, k), the voxels the restriction keeps; bits at
+                                        or above `levels` give CGDIR_E_INVAL */
     float sigma_fluid;               /* Gaussian sigma smoothing du (voxels); default 1 */
     float sigma_diff;                /* Gaussian sigma smoothing u (voxels); default 1 */
     float restrict_sigma;            /* Gaussian sigma of the pyramid restriction; default 1 */

@@ -133,6 +133,7 @@ hipError_t launch_prolong(const float *const uc[3], Dims dc, float *const uf[3],
                           hipStream_t s);
 hipError_t launch_pack_masks(const uint8_t *const *planes, int k, int64_t n, uint8_t *bits,
                              hipStream_t s);
+hipError_t launch_level_bits(const uint8_t *bits0, Dims d0, int level, uint8_t *out, Dims dc, hipStream_t s);
 hipError_t launch_uroi(const uint8_t *tbits, Dims d, const int margin[3], uint8_t *rowdist,
                        uint8_t *uroi, hipStream_t s);
 hipError_t launch_count(const uint8_t *m, int64_t n, uint8_t bitmask, int64_t *partials,

@@ -956,6 +956,21 @@ __global__ void __launch_bounds__(256) k_pack_masks(MaskPtrs m, int k, int64_t n
     bits[v] = (uint8_t)b;
 }
 
+// Structure bits at pyramid level l (contour terms below the finest level): the bits of the
+// finest voxel that coarse voxel (i, j, k) stands for, (2^l i, 2^l j, 2^l k), the voxel every
+// restriction step keeps.  One thread per coarse voxel; dc = level_dims(d0, l).
+__global__ void __launch_bounds__(256) k_level_bits(const uint8_t *__restrict__ bits0, Dims d0, int shift,
+                                                    uint8_t *__restrict__ out, Dims dc)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= dc.n()) return;
+    const int i = (int)(v % dc.nx);
+    const int j = (int)((v / dc.nx) % dc.ny);
+    const int l = (int)(v / ((int64_t)dc.nx * dc.ny));
+    const int64_t f = (int64_t)(i << shift) + (int64_t)d0.nx * ((int64_t)(j << shift) + (int64_t)d0.ny * (l << shift));
+    out[v] = bits0[f];
+}
+
 // distance along x to the nearest voxel whose bits intersect `sel`, capped at 255
 __global__ void __launch_bounds__(256) k_rowdist(const uint8_t *__restrict__ bits, uint8_t sel,
                                                  Dims d, uint8_t *__restrict__ dist)
@@ -1245,6 +1260,18 @@ hipError_t launch_pack_masks(const uint8_t *const *planes, int k, int64_t n, uin
     MaskPtrs m{};
     for (int i = 0; i < k; ++i) m.p[i] = planes[i];
     hipLaunchKernelGGL(k_pack_masks, dim3(blocks_for(n, 256)), dim3(256), 0, s, m, k, n, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_bits(const uint8_t *bits0, Dims d0, int level, uint8_t *out, Dims dc, hipStream_t s)
+{
+    if (level < 1 || level >= 31) return hipErrorInvalidValue;
+    // every kept index 2^l (ceil(n / 2^l) - 1) is below n
+    if ((((int64_t)dc.nx - 1) << level) >= d0.nx || (((int64_t)dc.ny - 1) << level) >= d0.ny ||
+        (((int64_t)dc.nz - 1) << level) >= d0.nz)
+        return hipErrorInvalidValue;
+    if (dc.n() == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_level_bits, dim3(blocks_for(dc.n(), 256)), dim3(256), 0, s, bits0, d0, level, out, dc);
     return hipGetLastError();
 }
 

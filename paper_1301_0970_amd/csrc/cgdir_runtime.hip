@@ -171,6 +171,11 @@ size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, 
     if (k > 0) {  // bit-planes, brick occupancy, stencil structure bits, K_i~
         b += 2 * align_up(n0) + align_up((size_t)brick_dims(d0).n());
         b += align_up(n0) + align_up(n0 * sizeof(float));
+        for (int l = 1; l < p.levels; ++l)  // bit-planes and occupancy of coarse contour levels
+            if ((p.contour_level_mask >> l) & 1u) {
+                const Dims dl = level_dims(d0, l);
+                b += 2 * align_up((size_t)dl.n()) + align_up((size_t)brick_dims(dl).n());
+            }
     }
     if (want_delta(p)) {
         b += align_up(n0);  // UROI
@@ -450,7 +455,7 @@ int check_params(const cgdir_params &p, int k)
     if (p.levels < 1 || p.levels > CGDIR_MAX_LEVELS) return CGDIR_E_INVAL;
     for (int l = 0; l < p.levels; ++l)
         if (p.iters[l] < 0) return CGDIR_E_INVAL;
-    if (p.contour_level_mask > 1u) return CGDIR_E_UNIMPL;
+    if (p.contour_level_mask >> p.levels) return CGDIR_E_INVAL;  // a bit for a level that does not exist
     const bool voxel_units = p.spacing[0] == 0.f && p.spacing[1] == 0.f && p.spacing[2] == 0.f;
     if (!voxel_units) {
         for (int a = 0; a < 3; ++a)
@@ -540,6 +545,9 @@ struct Job {
     std::vector<void *> allocs;
     const float *I0[CGDIR_MAX_LEVELS] = {}, *T0[CGDIR_MAX_LEVELS] = {};
     uint8_t *mbits = nullptr, *tbits = nullptr, *uroi = nullptr, *mocc = nullptr;
+    // per level with contour terms: moving and target bit-planes, moving brick occupancy
+    // (index 0 = the finest level's mbits, tbits, mocc)
+    uint8_t *mbitsL[CGDIR_MAX_LEVELS] = {}, *tbitsL[CGDIR_MAX_LEVELS] = {}, *moccL[CGDIR_MAX_LEVELS] = {};
     float *ubuf = nullptr, *ucbuf = nullptr;
     float *wI0 = nullptr, *Kbuf = nullptr;
     uint8_t *Fbuf = nullptr;
@@ -661,6 +669,17 @@ struct Job {
             Fbuf = (uint8_t *)take(n0);
             Kbuf = (float *)take(n0 * sizeof(float));
             ok = ok && mbits && tbits && mocc && Fbuf && Kbuf;
+            mbitsL[0] = mbits;
+            tbitsL[0] = tbits;
+            moccL[0] = mocc;
+            for (int l = 1; l < L; ++l) {
+                if (!contour_at(l)) continue;
+                const Dims dl = level_dims(d0, l);
+                mbitsL[l] = (uint8_t *)take((size_t)dl.n());
+                tbitsL[l] = (uint8_t *)take((size_t)dl.n());
+                moccL[l] = (uint8_t *)take((size_t)brick_dims(dl).n());
+                ok = ok && mbitsL[l] && tbitsL[l] && moccL[l];
+            }
         }
         if (delta_on) {
             uroi = (uint8_t *)take(n0);
@@ -721,6 +740,16 @@ struct Job {
                 if (m.where == CGDIR_HOST) HIP_TRY(hipStreamSynchronize(s));  // staging reused next side
             }
             HIP_TRY(timed(ctx, K_PACK * 8 + 7, (double)n0, [&] { return launch_brick_occupancy(mbits, d0, mocc, s); }));
+            for (int l = 1; l < L; ++l) {  // coarse levels with contour terms
+                if (!contour_at(l)) continue;
+                const Dims dl = level_dims(d0, l);
+                HIP_TRY(timed(ctx, K_PACK * 8 + l, (double)dl.n(), [&] {
+                    hipError_t e = launch_level_bits(mbits, d0, l, mbitsL[l], dl, s);
+                    if (e == hipSuccess) e = launch_level_bits(tbits, d0, l, tbitsL[l], dl, s);
+                    if (e == hipSuccess) e = launch_brick_occupancy(mbitsL[l], dl, moccL[l], s);
+                    return e;
+                }));
+            }
         }
         // the u_c buffer (12 bytes per voxel) is scratch until the first iteration
         uint8_t *rowdist = (uint8_t *)ucbuf + n0;
@@ -793,8 +822,8 @@ struct Job {
         const bool contour = contour_at(level);
         WarpArgs w{};
         w.I0 = I0[level];
-        w.mbits = contour ? mbits : nullptr;
-        w.mocc = contour ? mocc : nullptr;
+        w.mbits = contour ? mbitsL[level] : nullptr;
+        w.mocc = contour ? moccL[level] : nullptr;
         w.wI0 = wI0;
         w.F = contour ? Fbuf : nullptr;
         w.K = contour ? Kbuf : nullptr;
@@ -839,10 +868,10 @@ struct Job {
         sa.F = contour ? Fbuf : nullptr;
         sa.K = contour ? Kbuf : nullptr;
         sa.T0 = T0[level];
-        sa.tbits = contour ? tbits : nullptr;
+        sa.tbits = contour ? tbitsL[level] : nullptr;
         sa.uroi = metric() ? uroi : nullptr;
         sa.I0 = I0[level];
-        sa.mbits = contour ? mbits : nullptr;
+        sa.mbits = contour ? mbitsL[level] : nullptr;
         for (int c = 0; c < 3; ++c) {
             sa.u[c] = comp(ubuf, c);
             sa.uc[c] = comp(ucbuf, c);

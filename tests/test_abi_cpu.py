@@ -44,6 +44,11 @@ def test_footprint():
     # bits and K_i~ (5 B), coarse images (8 B x (1/8 + 1/64))
     assert 35 * n <= fp <= 37 * n
     assert cgdir.footprint(512, 512, 128, 0, p) < fp
+    # contour terms at both coarse levels: their bit-planes (2 B x (1/8 + 1/64)) and occupancy
+    pc = cgdir.make_params(levels=3, iters=(150, 150, 150), contour_level_mask=7)
+    extra = cgdir.footprint(512, 512, 128, 8, pc) - fp
+    assert 2 * n * (1 / 8 + 1 / 64) <= extra <= 2 * n * (1 / 8 + 1 / 64) + (1 << 20)
+    assert cgdir.footprint(512, 512, 128, 0, pc) == cgdir.footprint(512, 512, 128, 0, p)
     assert cgdir.footprint(0, 5, 5, 1, p) == 0
     assert cgdir.footprint(5, 5, 5, 9, p) == 0
 

@@ -197,6 +197,48 @@ def test_restrict_and_prolong_through_schedule(ctx, orc):
     assert np.abs(ug - uo).max() <= STEP_TOL * 2  # prolongation doubles the coarse field
 
 
+@pytest.mark.parametrize("levels,mask,it", [(2, 2, (0, 1)), (3, 4, (0, 0, 1)), (3, 6, (0, 1, 1))],
+                         ids=["L2 coarse", "L3 coarsest", "L3 both coarse"])
+def test_contour_terms_at_coarse_levels_schedule(ctx, orc, levels, mask, it):
+    """Contour terms below the finest level (masks taken at the voxels the restriction
+    keeps): with single iterations at coarse levels and none at the finest, the output is
+    those iterations prolongated, at 1e-4 per doubling.  Ragged dims exercise the ceil(n/2)
+    levels; the overlapping structures exercise the multi-structure path at a coarse level."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.pelvis_pair(dims=(77, 66, 31), amp=3.0, k=3, levels=levels, iters=1, bulge=0.0)
+    rng = np.random.default_rng(levels * 10 + mask)
+    grow = lambda b: np.maximum(b, np.roll(b, 3, axis=2))             # noqa: E731
+    pair.target_masks = np.stack([pair.target_masks[0], grow(pair.target_masks[0]), pair.target_masks[2]])
+    pair.moving_masks = np.stack([pair.moving_masks[0], grow(pair.moving_masks[0]), pair.moving_masks[2]])
+    lam = [float(v) for v in rng.uniform(1e-3, 5e-3, 3)]
+    prm = cgdir.params_for_pair(pair, iters=it, contour_level_mask=mask, lambdas=lam)
+    say("coarse contour schedule levels=%d mask=%d" % (levels, mask))
+    ug = gpu_register(ctx, pair, prm)
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, iters=it, contour_level_mask=mask, lambdas=lam))
+    u0, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, iters=it, contour_level_mask=0, lambdas=lam))
+    assert np.abs(uo - u0).max() > 1e-3         # the contour terms act at that level
+    err = np.abs(ug - uo).max()
+    say("  max err %.3g" % err)
+    assert err <= STEP_TOL * 2 ** (levels - 1)
+
+
+def test_full_run_pyramid_contour_terms_at_every_level(ctx, orc):
+    """Three levels with contour terms at each (the finest as in Algorithm A, the coarse two
+    on masks at the kept voxels), 30 iterations per level."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(99, 83, 45), amp=5.0, k=4, levels=3, iters=30)
+    say("full run pyramid 99x83x45 3x30, contour terms at every level")
+    ug = gpu_register(ctx, pair, cgdir.params_for_pair(pair, contour_level_mask=7))
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, contour_level_mask=7))
+    err = np.abs(ug - uo).max()
+    rms = np.sqrt(((orc.warp(pair.moving, ug) - orc.warp(pair.moving, uo)) ** 2).mean())
+    say("  final max err %.3g voxel, warped rms %.3g HU" % (err, rms))
+    assert err <= FINAL_TOL and rms <= WARP_RMS_TOL
+
+
 def test_identity_stays_zero(ctx):
     """P4 on the GPU: identical images and masks give exactly u = 0."""
     from paper_1301_0970_amd import cgdir
@@ -302,9 +344,9 @@ def test_invalid_arguments(ctx):
         with pytest.raises(cgdir.CgdirError) as e:
             ctx.register(t, m, tm, mm, cgdir.params_for_pair(pair, **bad))
         assert e.value.code == cgdir.E_INVAL, bad
-    with pytest.raises(cgdir.CgdirError) as e:
+    with pytest.raises(cgdir.CgdirError) as e:   # contour terms at a level that does not exist
         ctx.register(t, m, tm, mm, cgdir.params_for_pair(pair, contour_level_mask=2))
-    assert e.value.code == cgdir.E_UNIMPL
+    assert e.value.code == cgdir.E_INVAL
     big = torch.zeros((256, 1024, 1024), dtype=torch.float32, device="cuda")
     one = cgdir.make_params(levels=1, iters=(1,))
     assert cgdir.footprint(1024, 1024, 256, 0, one) > (6 << 30)   # more than the context's pool

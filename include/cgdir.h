@@ -35,6 +35,7 @@ extern "C" {
 
 #define CGDIR_MAX_STRUCTS 8 /* structures per registration (bits of one mask byte) */
 #define CGDIR_MAX_LEVELS 6  /* pyramid levels */
+#define CGDIR_KEEP_FINISHED 4096 /* served requests whose final status a context keeps */
 
 enum cgdir_code {
     CGDIR_OK = 0,
@@ -192,7 +193,9 @@ int cgdir_register_batch(cgdir_ctx *ctx, int n, const cgdir_request *reqs, int *
  * slot is free and the pool holds their footprint; admitted requests advance together,
  * iteration by iteration, and new ones join between iterations (continuous batching).
  * Returns CGDIR_E_NOMEM at once if the footprint exceeds the whole pool, CGDIR_E_INVAL
- * for invalid arguments.  *ticket identifies the request. */
+ * for invalid arguments.  *ticket identifies the request.  A context keeps the status of
+ * its CGDIR_KEEP_FINISHED most recently finished requests (done, failed or cancelled); an
+ * older ticket is then unknown to cgdir_poll / cgdir_wait / cgdir_cancel. */
 int cgdir_submit(cgdir_ctx *ctx, const cgdir_request *req, uint64_t *ticket);
 
 typedef struct cgdir_status {

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libcgdir.so")
 
 MAX_STRUCTS = 8
 MAX_LEVELS = 6
+KEEP_FINISHED = 4096   # served requests whose final status a context keeps
 
 OK = 0
 E_INVAL, E_NOMEM, E_HIP, E_BUSY, E_NOTFOUND, E_CANCELLED, E_NONFINITE, E_UNIMPL, E_TIMEOUT = (
@@ -408,6 +409,8 @@ class Context:
     def poll(self, ticket):
         rc, st = poll(self.handle, ticket)
         _check(rc, "cgdir_poll")
+        if st.state in (DONE, FAILED, CANCELLED):   # the library is done with the tensors
+            self._keep.pop(ticket, None)
         return st
 
     def wait(self, ticket, timeout_ns=-1):

@@ -350,7 +350,10 @@ struct cgdir_ctx {
     uint64_t next_ticket = 1;
     std::deque<uint64_t> queue;
     struct Request;
-    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    // records of queued, running and the CGDIR_KEEP_FINISHED latest finished requests
+    // (shared: a waiter keeps its record alive while it sleeps)
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
+    std::deque<uint64_t> finished_order;
     std::mutex launch_mu;  // keeps each job's launch sequence contiguous on the stream
 
     // pinned records, allocated in chunks and recycled
@@ -1141,12 +1144,19 @@ struct cgdir_ctx::Request {
 namespace cgdir {
 namespace {
 
-void finish_request(cgdir_ctx::Request *r, int code)
+// Final state of a request (under ctx->mu); the oldest finished records beyond
+// CGDIR_KEEP_FINISHED are dropped.
+void finish_request(cgdir_ctx *c, cgdir_ctx::Request *r, int code)
 {
     r->job.release();
     r->error = code;
     r->state = code == CGDIR_OK ? CGDIR_DONE : (code == CGDIR_E_CANCELLED ? CGDIR_CANCELLED : CGDIR_FAILED);
     r->t_done = now_ns();
+    c->finished_order.push_back(r->ticket);
+    while (c->finished_order.size() > (size_t)CGDIR_KEEP_FINISHED) {
+        c->reqs.erase(c->finished_order.front());
+        c->finished_order.pop_front();
+    }
 }
 
 // The serving loop: FIFO admission by pool footprint and free slots, then ticks in which
@@ -1188,7 +1198,7 @@ void scheduler(cgdir_ctx *c)
                 if (rc == CGDIR_E_NOMEM) break;  // the head of the queue waits for memory
                 c->queue.pop_front();
                 if (rc != CGDIR_OK) {
-                    finish_request(r, rc);
+                    finish_request(c, r, rc);
                     c->cv.notify_all();
                     continue;
                 }
@@ -1203,7 +1213,7 @@ void scheduler(cgdir_ctx *c)
             if (rc != CGDIR_OK) {
                 hipStreamSynchronize(c->stream);  // set-up work in flight may still use its memory
                 std::lock_guard<std::mutex> lk(c->mu);
-                finish_request(r, rc);
+                finish_request(c, r, rc);
                 c->cv.notify_all();
                 continue;
             }
@@ -1261,10 +1271,11 @@ void scheduler(cgdir_ctx *c)
             r->iter = r->job.iter;
             r->last_delta = r->job.last_delta;
             if (r->emitted && (!r->done_ev || hipEventQuery(r->done_ev) == hipSuccess)) {
+                if (!r->done_ev) hipStreamSynchronize(c->stream);  // no event: wait for its copies
                 const int rc = r->error != CGDIR_OK ? r->error : r->job.conclude();
                 if (r->done_ev) spare.push_back(r->done_ev);
                 r->done_ev = nullptr;
-                finish_request(r, rc);
+                finish_request(c, r, rc);
                 active.erase(active.begin() + i);
                 c->cv.notify_all();
             } else {
@@ -1388,7 +1399,7 @@ int cgdir_destroy(cgdir_ctx *c)
         for (uint64_t t : c->queue) {
             auto it = c->reqs.find(t);
             if (it != c->reqs.end() && it->second->state == CGDIR_QUEUED)
-                finish_request(it->second.get(), CGDIR_E_CANCELLED);
+                finish_request(c, it->second.get(), CGDIR_E_CANCELLED);
         }
         c->queue.clear();
         c->stopping = true;
@@ -1764,7 +1775,7 @@ int cgdir_evaluate(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume 
 int cgdir_submit(cgdir_ctx *c, const cgdir_request *req, uint64_t *ticket)
 {
     if (!c || !req || !ticket) return CGDIR_E_INVAL;
-    std::unique_ptr<cgdir_ctx::Request> r(new cgdir_ctx::Request());
+    std::shared_ptr<cgdir_ctx::Request> r = std::make_shared<cgdir_ctx::Request>();
     CG_TRY(r->job.init(c, *req));
     if (r->job.need() > c->pool.size()) return CGDIR_E_NOMEM;
     r->t_submit = now_ns();
@@ -1808,7 +1819,7 @@ int cgdir_cancel(cgdir_ctx *c, uint64_t ticket)
     auto it = c->reqs.find(ticket);
     if (it == c->reqs.end()) return CGDIR_E_NOTFOUND;
     if (it->second->state != CGDIR_QUEUED) return CGDIR_E_BUSY;
-    finish_request(it->second.get(), CGDIR_E_CANCELLED);
+    finish_request(c, it->second.get(), CGDIR_E_CANCELLED);
     c->cv.notify_all();
     return CGDIR_OK;
 }
@@ -1820,7 +1831,7 @@ int cgdir_wait(cgdir_ctx *c, uint64_t ticket, int64_t timeout_ns)
     auto final_state = [&](int s) { return s == CGDIR_DONE || s == CGDIR_FAILED || s == CGDIR_CANCELLED; };
     auto it = c->reqs.find(ticket);
     if (it == c->reqs.end()) return CGDIR_E_NOTFOUND;
-    cgdir_ctx::Request *r = it->second.get();
+    const std::shared_ptr<cgdir_ctx::Request> r = it->second;  // alive while this thread sleeps
     auto pred = [&] { return final_state(r->state); };
     if (timeout_ns < 0) {
         c->cv.wait(lk, pred);

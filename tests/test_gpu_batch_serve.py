@@ -157,6 +157,36 @@ def test_batch_of_many_small_pairs_spans_several_launches():
             np.testing.assert_array_equal(a, o.cpu().numpy())
 
 
+def test_served_records_are_bounded():
+    """A context keeps the final status of its KEEP_FINISHED latest finished requests: after
+    more tiny served registrations than that, the oldest tickets are unknown, the latest are
+    done, and their fields equal the same registration alone."""
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair(dims=(8, 8, 4), amp=0.5, iters=1, seed=5)
+    items = _items([pair])[0]
+    prm = cgdir.params_for_pair(pair)
+    n = cgdir.KEEP_FINISHED + 40
+    with cgdir.Context(1 << 30, max_slots=16) as ctx:
+        ref = ctx.register(*items, prm=prm).cpu().numpy()
+        outs = [torch.empty((3,) + tuple(pair.target.shape), device="cuda") for _ in range(n)]
+        say("served x%d tiny" % n)
+        tickets = [ctx.submit(*items, prm, o) for o in outs]
+        for t in tickets[-64:]:
+            assert ctx.wait(t) == cgdir.OK
+        for t in tickets:            # every request has finished by now
+            rc, st = cgdir.poll(ctx.handle, t)
+            assert rc in (cgdir.OK, cgdir.E_NOTFOUND)
+            if rc == cgdir.OK:
+                assert st.state == cgdir.DONE
+        known = [cgdir.poll(ctx.handle, t)[0] == cgdir.OK for t in tickets]
+        assert sum(known) == cgdir.KEEP_FINISHED and not any(known[:40]) and all(known[-64:])
+        assert cgdir.wait(ctx.handle, tickets[0]) == cgdir.E_NOTFOUND
+        assert cgdir.cancel(ctx.handle, tickets[0]) == cgdir.E_NOTFOUND
+        for o in outs[:3] + outs[-3:]:
+            np.testing.assert_array_equal(o.cpu().numpy(), ref)
+
+
 def test_early_stop_on_the_device_alone_batched_and_served():
     """The stopping rule runs on the device: each pair stops at its own iteration whether it
     runs alone, batched or served, and the launches after its stop leave its field as it was

@@ -70,3 +70,57 @@ def test_create_rejects_bad_descriptions():
     assert lib.cgdir_create(ctypes.byref(h), ctypes.byref(d)) == cgdir.E_INVAL
     assert lib.cgdir_destroy(None) == cgdir.E_INVAL
     assert lib.cgdir_register(None, None, None, None, None, None, None, 0) == cgdir.E_INVAL
+
+
+# C struct of each ctypes mirror in the binding, and the binding's field names that differ
+# from the header's
+_STRUCTS = [("cgdir_ctx_desc", "ctx_desc"), ("cgdir_volume", "volume"), ("cgdir_masks", "masks"),
+            ("cgdir_params", "params"), ("cgdir_request", "request"), ("cgdir_status", "status"),
+            ("cgdir_kernel_stat", "kernel_stat"), ("cgdir_eval_params", "eval_params"),
+            ("cgdir_eval", "eval_result")]
+_RENAMED = {"lambda_": "lambda"}
+
+
+def test_header_is_c99_and_layouts_match_the_binding(tmp_path):
+    """include/cgdir.h compiles as strict C99; a C program linked against libcgdir.so sees the
+    same struct sizes and field offsets as the Python binding's ctypes mirrors, and calls the
+    host-only entry points (no GPU needed)."""
+    import shutil
+    import subprocess
+    from paper_1301_0970_amd import cgdir
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "cgdir.h"', "int main(void) {"]
+    expect = {}
+    for cname, pyname in _STRUCTS:
+        py = getattr(cgdir, pyname)
+        lines.append('    printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        expect[cname] = ctypes.sizeof(py)
+        for f in py._fields_:
+            field = _RENAMED.get(f[0], f[0])
+            key = "%s.%s" % (cname, field)
+            lines.append('    printf("%s %%zu\\n", offsetof(%s, %s));' % (key, cname, field))
+            expect[key] = getattr(py, f[0]).offset
+    lines += ["    cgdir_params p;", "    cgdir_params_default(&p);",
+              '    printf("levels %d\\n", p.levels);',
+              '    printf("footprint %zu\\n", cgdir_footprint(64, 64, 32, 1, &p));',
+              '    printf("strerror %s\\n", cgdir_strerror(CGDIR_E_NOMEM));',
+              "    return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    libdir = os.path.dirname(cgdir.LIB_PATH)
+    exe = tmp_path / "abi"
+    subprocess.run([cc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-L", libdir, "-lcgdir", "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=60).stdout
+    got = {}
+    for line in out.splitlines():
+        key, _, val = line.partition(" ")
+        got[key] = val
+    for key, v in expect.items():
+        assert int(got[key]) == v, key
+    p = cgdir.params_default()
+    assert int(got["levels"]) == p.levels
+    assert int(got["footprint"]) == cgdir.footprint(64, 64, 32, 1, p)
+    assert got["strerror"] == cgdir.strerror(cgdir.E_NOMEM)

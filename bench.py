@@ -260,7 +260,8 @@ def warm_start(cgdir, torch, pair, pool, iters=30):
 
 def batched(cgdir, P, torch, n_pairs):
     """The uneven batch (sizes and structure counts drawn per pair): all pairs in one
-    cgdir_register_batch call vs the same pairs registered one at a time."""
+    cgdir_register_batch call vs the same pairs registered one at a time, both timed after a
+    pass of each that lets the autotuner settle every tile-shape group they use."""
     specs = P.batch_specs(n_pairs)
     pairs = [P.from_spec(s) for s in specs]
     dev = torch.device("cuda")
@@ -272,7 +273,9 @@ def batched(cgdir, P, torch, n_pairs):
     vi = sum(p.voxel_iterations() for p in pairs)
     pool = sum(cgdir.footprint(*p.dims, p.k, pr) for p, pr in zip(pairs, prms)) + (256 << 20)
     with cgdir.Context(pool) as ctx:
-        ctx.register(*items[0], prms[0], outs[0])      # warm-up
+        for it, pr, o in zip(items, prms, outs):        # warm-up: tile shapes of every pair
+            ctx.register(*it, pr, o)
+        ctx.register_batch(items, prms, outs)           # and of every batched launch group
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for it, pr, o in zip(items, prms, outs):

@@ -282,6 +282,7 @@ def batched(cgdir, P, torch, n_pairs):
             ctx.register(*it, pr, o)
         torch.cuda.synchronize()
         serial = time.perf_counter() - t0
+        time.sleep(0.05)   # an idle gap that marks the timed batched run in a kernel trace
         t0 = time.perf_counter()
         rc, st = ctx.register_batch(items, prms, outs)
         torch.cuda.synchronize()

@@ -194,9 +194,12 @@ const char *kKernelNames[K_COUNT] = {"step", "smooth", "delta", "restrict", "pro
 
 // ------------------------------------------------------------------ tile autotuner
 // A pair's results do not depend on the tile shape of any kernel, so the first launches of
-// each (kernel, shapes) group rotate through candidate shapes, each timed with HIP events
-// on the stream; once every candidate has been timed, the fastest is kept for the group for
-// the rest of the context's life.  CGDIR_TUNE fixes the shapes instead.
+// each group rotate through candidate shapes, each timed with HIP events on the stream; once
+// every candidate has been timed, the fastest (per voxel of its launch) is kept for the group
+// for the rest of the context's life.  A group is (kernel, radius, dims of the launch's
+// largest pair, log2 of the launch's voxel count): launches that mix different pairs, as
+// served requests join and leave, fall into few groups, while a launch of many small pairs
+// is still tuned apart from one small pair alone.  CGDIR_TUNE fixes the shapes instead.
 struct TileCfg {
     int ty, tz;
 };
@@ -231,9 +234,9 @@ class Tuner {
             for (int i = 1; i < nc; ++i)
                 if (e.ms[i] < e.ms[e.best]) e.best = i;
             if (log) {
-                std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.4f ms) |", key.c_str(), c[e.best].ty,
+                std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.5f ms per Mvoxel) |", key.c_str(), c[e.best].ty,
                              c[e.best].tz, e.ms[e.best]);
-                for (int i = 0; i < nc; ++i) std::fprintf(stderr, " %d,%d:%.4f", c[i].ty, c[i].tz, e.ms[i]);
+                for (int i = 0; i < nc; ++i) std::fprintf(stderr, " %d,%d:%.5f", c[i].ty, c[i].tz, e.ms[i]);
                 std::fprintf(stderr, "\n");
             }
             return c[e.best];
@@ -244,9 +247,9 @@ class Tuner {
         }
         return c[0];
     }
-    void record(const std::string &key, int cand, hipEvent_t a, hipEvent_t b)
+    void record(const std::string &key, int cand, hipEvent_t a, hipEvent_t b, double voxels)
     {
-        table_[key].pending.push_back({cand, a, b});
+        table_[key].pending.push_back({cand, a, b, voxels > 0.0 ? 1e6 / voxels : 1.0});
     }
     hipEvent_t event()
     {
@@ -276,6 +279,7 @@ class Tuner {
     struct Pending {
         int cand;
         hipEvent_t a, b;
+        double scale;  // to ms per million voxels of the launch
     };
     struct Entry {
         int next = 0, best = -1;
@@ -288,7 +292,7 @@ class Tuner {
             Pending &p = e.pending[i];
             if (hipEventQuery(p.b) == hipSuccess) {
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) e.ms[p.cand] = ms;
+                if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) e.ms[p.cand] = (float)(ms * p.scale);
                 else e.ms[p.cand] = 1e30f;
                 spare_.push_back(p.a);
                 spare_.push_back(p.b);
@@ -1045,23 +1049,27 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
         if (jobs[i]->level != lvl) lvl = 6;
 
     auto shapes_key = [&](char kind, int radius, const int *idx, int n) {
-        std::string key(1, kind);
-        key += std::to_string(radius);
+        Dims big{0, 0, 0};
+        double total = 0.0;
         for (int q = 0; q < n; ++q) {
             const Dims d = level_dims(jobs[idx[q]]->d0, jobs[idx[q]]->level);
-            key += ':' + std::to_string(d.nx) + 'x' + std::to_string(d.ny) + 'x' + std::to_string(d.nz);
+            total += (double)d.n();
+            if (d.n() > big.n()) big = d;
         }
+        std::string key(1, kind);
+        key += std::to_string(radius) + ':' + std::to_string(big.nx) + 'x' + std::to_string(big.ny) + 'x' +
+               std::to_string(big.nz) + '/' + std::to_string((int)std::floor(std::log2(std::max(total, 1.0))));
         return key;
     };
     // a launch, timed for the tuner when it asks
-    auto tuned = [&](bool measure_it, const std::string &key, int cand, auto &&fn) -> hipError_t {
+    auto tuned = [&](bool measure_it, const std::string &key, int cand, double voxels, auto &&fn) -> hipError_t {
         if (!measure_it) return fn();
         hipEvent_t ea = c->tuner.event(), eb = c->tuner.event();
         if (!ea || !eb) return fn();
         hipEventRecord(ea, s);
         const hipError_t e = fn();
         hipEventRecord(eb, s);
-        c->tuner.record(key, cand, ea, eb);
+        c->tuner.record(key, cand, ea, eb, voxels);
         return e;
     };
 
@@ -1086,7 +1094,7 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
                 vox += (double)sb.d[q].d.n();
             }
             HIP_TRY(timed(c, K_STEP * 8 + lvl, vox, [&] {
-                return tuned(cand >= 0, key, cand, [&] { return launch_step_batch(sb, g.first, cfg.ty, s); });
+                return tuned(cand >= 0, key, cand, vox, [&] { return launch_step_batch(sb, g.first, cfg.ty, s); });
             }));
         }
     }
@@ -1116,7 +1124,7 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
                 vox += (double)sb.d[q].d.n();
             }
             HIP_TRY(timed(c, K_SMOOTH * 8 + lvl, vox, [&] {
-                return tuned(cand >= 0, key, cand, [&] { return launch_smooth_batch(sb, g.first, cfg.ty, s); });
+                return tuned(cand >= 0, key, cand, vox, [&] { return launch_smooth_batch(sb, g.first, cfg.ty, s); });
             }));
         }
     }

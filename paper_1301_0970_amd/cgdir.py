@@ -287,7 +287,12 @@ class Context:
         self._torch = torch
         self.device = torch.device("cuda", device)
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # The library orders its work on its own stream only.  Every call first makes that
+        # stream wait for the caller's current stream (_order), so that device inputs that
+        # torch is still computing are complete before the library reads them.  (torch's
+        # default stream has the handle 0, which the library would replace by a stream of its
+        # own, so the context gets a dedicated stream of default priority instead.)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         d = ctx_desc(device=device, stream=self.stream.cuda_stream, pool=self.pool.data_ptr(),
                      pool_bytes=int(pool_bytes), max_slots=int(max_slots),
                      flags=CTX_PROFILE if profile else 0)
@@ -306,22 +311,46 @@ class Context:
         self.close()
 
     # -- marshalling
+    def _order(self):
+        cur = self._torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
     def _where(self, t):
         return DEVICE if t.is_cuda else HOST
 
+    def _plain(self, t, dtype, what):
+        """The library reads raw, densely packed memory: dtype and layout must match."""
+        if t.dtype != dtype:
+            raise ValueError("%s must be %s, not %s" % (what, dtype, t.dtype))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous (x fastest)" % what)
+        return t
+
+    def _field(self, t, like, what):
+        """A field of three float32 planes of like's voxels (the library reads or writes
+        3 * like.numel() floats; the volumes themselves it checks)."""
+        self._plain(t, self._torch.float32, what)
+        if t.numel() < 3 * like.numel():
+            raise ValueError("%s holds %d floats, fewer than 3 x %d" % (what, t.numel(), like.numel()))
+        return t
+
     def volume(self, t) -> volume:
+        self._plain(t, self._torch.float32, "a volume")
         nz, ny, nx = t.shape
         return volume(t.data_ptr(), nx, ny, nz, self._where(t))
 
     def masks(self, m, keep: list) -> masks:
         if m is None or m.shape[0] == 0:
             return masks(0, None, DEVICE)
+        self._plain(m, self._torch.uint8, "masks")
         k = m.shape[0]
         ptrs = (ctypes.c_void_p * k)(*[m[i].data_ptr() for i in range(k)])
         keep.append(ptrs)
         return masks(k, ptrs, self._where(m))
 
     def request(self, target, moving, target_masks, moving_masks, prm: params, out, keep) -> request:
+        self._field(out, target, "the output field")
         return request(self.volume(target), self.volume(moving), self.masks(target_masks, keep),
                        self.masks(moving_masks, keep), prm, out.data_ptr(), self._where(out))
 
@@ -334,10 +363,12 @@ class Context:
         prm = params.from_buffer_copy(prm) if prm is not None else params_default()
         if out is None:
             out = torch.empty((3,) + tuple(target.shape), dtype=torch.float32, device=target.device)
+        self._field(out, target, "the output field")
         keep = []
         hist = None
         done = ctypes.c_int(0)
         if initial is not None:
+            self._field(initial, target, "the initial field")
             prm.initial_dvf = initial.data_ptr()
             prm.initial_dvf_where = self._where(initial)
         if delta:
@@ -346,8 +377,9 @@ class Context:
         prm.iters_done = ctypes.pointer(done)
         tm = self.masks(target_masks, keep)
         mm = self.masks(moving_masks, keep)
-        rc = register(self.handle, self.volume(target), self.volume(moving), tm, mm, prm,
-                      out.data_ptr(), self._where(out))
+        tv, mv = self.volume(target), self.volume(moving)
+        self._order()
+        rc = register(self.handle, tv, mv, tm, mm, prm, out.data_ptr(), self._where(out))
         _check(rc, "cgdir_register")
         if delta:
             return out, [hist[i] for i in range(done.value)], done.value
@@ -357,8 +389,17 @@ class Context:
         torch = self._torch
         if out is None:
             out = torch.empty_like(src)
-        _check(warp(self.handle, self.volume(src), dvf.data_ptr(), mode, out.data_ptr()), "cgdir_warp")
+        sv = self.volume(src) if mode == WARP_LINEAR else self._mask_volume(src)
+        self._field(dvf, src, "the field")
+        self._plain(out, src.dtype, "the output")
+        self._order()
+        _check(warp(self.handle, sv, dvf.data_ptr(), mode, out.data_ptr()), "cgdir_warp")
         return out
+
+    def _mask_volume(self, t) -> volume:
+        self._plain(t, self._torch.uint8, "a mask")
+        nz, ny, nx = t.shape
+        return volume(t.data_ptr(), nx, ny, nz, self._where(t))
 
     def evaluate(self, target, moving, target_masks, moving_masks, dvf, spacing=None,
                  opening_radius=None, uroi_margin=None) -> dict:
@@ -374,10 +415,12 @@ class Context:
             ep.uroi_margin[:] = [int(v) for v in uroi_margin]
         keep = []
         res = eval_result()
-        rc = LIB.cgdir_evaluate(self.handle, ctypes.byref(self.volume(target)), ctypes.byref(self.volume(moving)),
-                                ctypes.byref(self.masks(target_masks, keep)),
-                                ctypes.byref(self.masks(moving_masks, keep)), dvf.data_ptr(),
-                                self._where(dvf), ctypes.byref(ep), ctypes.byref(res))
+        tv, mv = self.volume(target), self.volume(moving)
+        tm, mm = self.masks(target_masks, keep), self.masks(moving_masks, keep)
+        self._field(dvf, target, "the field")
+        self._order()
+        rc = LIB.cgdir_evaluate(self.handle, ctypes.byref(tv), ctypes.byref(mv), ctypes.byref(tm), ctypes.byref(mm),
+                                dvf.data_ptr(), self._where(dvf), ctypes.byref(ep), ctypes.byref(res))
         _check(rc, "cgdir_evaluate")
         out = {"whole": {"rms_id": res.rms_id, "cc": res.cc, "voxels": res.voxels}, "structures": []}
         if res.k:
@@ -395,12 +438,14 @@ class Context:
         keep = []
         reqs = [self.request(t, m, tm, mm, p, o, keep) for (t, m, tm, mm), p, o in zip(items, prms, outs)]
         st = (ctypes.c_int * len(reqs))()
+        self._order()
         rc = register_batch(self.handle, reqs, st)
         return rc, [st[i] for i in range(len(reqs))]
 
     def submit(self, target, moving, target_masks, moving_masks, prm, out):
         keep = []
         req = self.request(target, moving, target_masks, moving_masks, prm, out, keep)
+        self._order()
         rc, t = submit(self.handle, req)
         _check(rc, "cgdir_submit")
         self._keep[t] = (keep, target, moving, target_masks, moving_masks, out)

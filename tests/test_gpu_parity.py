@@ -355,6 +355,30 @@ def test_invalid_arguments(ctx):
     assert e.value.code == cgdir.E_NOMEM
 
 
+def test_inputs_still_being_computed_on_the_torch_stream(ctx):
+    """The binding orders the library's stream after the caller's current stream: an input that
+    torch is still writing (behind a 20 ms spin on its stream) when register is called is read
+    only once written, and tensors of the wrong dtype or layout are refused."""
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair(dims=(96, 80, 40), amp=3.0, iters=4)
+    prm = cgdir.params_for_pair(pair)
+    t, m, tm, mm = dev(pair.target), dev(pair.moving), dev(pair.target_masks), dev(pair.moving_masks)
+    ref = ctx.register(t, m, tm, mm, prm).cpu().numpy()
+    say("inputs written behind a spin on the torch stream")
+    late = torch.zeros_like(m)
+    torch.cuda._sleep(50_000_000)   # bounded spin, about 20 ms
+    late.copy_(m)
+    got = ctx.register(t, late, tm, mm, prm).cpu().numpy()
+    np.testing.assert_array_equal(got, ref)
+    with pytest.raises(ValueError):
+        ctx.register(t, m.double(), tm, mm, prm)
+    with pytest.raises(ValueError):
+        ctx.register(t.transpose(1, 2), m.transpose(1, 2), None, None, prm)
+    with pytest.raises(ValueError):
+        ctx.register(t, m, tm, mm, prm, out=torch.empty((3, 2, 2, 2), device="cuda"))
+
+
 def test_nonfinite_input_reported(ctx):
     from paper_1301_0970_amd import cgdir
     pair = P.plain_pair(dims=(40, 36, 20), amp=1.0, iters=3)

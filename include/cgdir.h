@@ -59,7 +59,9 @@ enum cgdir_ctx_flags { CGDIR_CTX_PROFILE = 1 /* time every kernel launch with HI
 typedef struct cgdir_ctx cgdir_ctx;
 
 /* Context description.  `stream` is a hipStream_t on `device` (NULL: the library creates
- * one with default priority).  `pool`/`pool_bytes` is device memory the caller owns and
+ * one with default priority).  All of the context's device work runs on that stream and is
+ * ordered after nothing else: device inputs written on another stream must be complete (or
+ * that stream waited on) before a call reads them.  `pool`/`pool_bytes` is device memory the caller owns and
  * keeps alive until cgdir_destroy returns (pool NULL: the library allocates pool_bytes
  * itself at create time).  Every per-registration buffer is carved out of the pool, so
  * no registration call allocates device memory.  `max_slots` bounds the registrations

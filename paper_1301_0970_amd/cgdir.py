@@ -7,7 +7,7 @@ raises (there is no fallback implementation).
 
 Names mirror the C entry points: ``create``, ``destroy``, ``register``, ``warp``,
 ``register_batch``, ``submit``, ``poll``, ``cancel``, ``wait``, ``footprint``,
-``strerror``, ``params_default``, ``kernel_stats``.  :class:`Context` wraps them for
+``strerror``, ``params_default``, ``kernel_stats``, ``evaluate``.  :class:`Context` wraps them for
 torch tensors.
 """
 from __future__ import annotations
@@ -300,9 +300,15 @@ class Context:
         self._keep = {}
 
     def close(self):
-        if self.handle is not None:
+        if getattr(self, "handle", None) is not None:
             destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass
 
     def __enter__(self):
         return self
@@ -449,6 +455,11 @@ class Context:
         rc, t = submit(self.handle, req)
         _check(rc, "cgdir_submit")
         self._keep[t] = (keep, target, moving, target_masks, moving_masks, out)
+        if len(self._keep) > KEEP_FINISHED:   # tickets never waited on: drop finished ones
+            for old in list(self._keep)[: len(self._keep) - KEEP_FINISHED // 2]:
+                prc, st = poll(self.handle, old)
+                if prc == E_NOTFOUND or (prc == OK and st.state in (DONE, FAILED, CANCELLED)):
+                    self._keep.pop(old, None)
         return t
 
     def poll(self, ticket):

@@ -283,3 +283,40 @@ def test_concurrent_submitters_and_a_blocking_registration():
             np.testing.assert_array_equal(o, alone[q])
         np.testing.assert_array_equal(blocking[0], alone[2])
         np.testing.assert_array_equal(blocking[1], alone[0])
+
+
+def test_mixed_parameters_batched_and_served_equal_alone():
+    """Pairs whose parameters differ in every way a launch groups by or carries per pair
+    (physical spacing with sigma in mm, contour terms at coarse levels, automatic signs, the
+    device-side stopping rule, no structures, ragged sizes) give bitwise the same field alone,
+    in one batch and served together."""
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pairs = [P.head_neck_pair(dims=(70, 58, 30), amp=3.0, k=3, levels=2, iters=8, seed=61),
+             P.pelvis_pair(dims=(90, 66, 26), amp=3.0, k=4, levels=3, iters=5, bulge=0.0, seed=62),
+             P.plain_pair(dims=(61, 47, 23), amp=2.0, iters=25, seed=63),
+             P.head_neck_pair(dims=(50, 70, 34), amp=3.0, k=2, levels=2, iters=6, seed=64),
+             P.plain_pair(dims=(40, 36, 20), amp=2.0, iters=7, seed=65)]
+    prms = [cgdir.params_for_pair(pairs[0], spacing=(1.97, 1.97, 2.5), sigma_fluid=2.0, sigma_diff=2.0),
+            cgdir.params_for_pair(pairs[1], contour_level_mask=7, signs=[0, 1, 0, -1]),
+            cgdir.params_for_pair(pairs[2], stop_mode=1, stop_eps=1e-3),
+            cgdir.params_for_pair(pairs[3], spacing=(1.2, 1.2, 3.0), contour_level_mask=3),
+            cgdir.params_for_pair(pairs[4], lambdas=[0.0] * pairs[4].k)]
+    items = _items(pairs)
+    items[4] = items[4][:2] + (None, None)   # plain demons: no structures
+    with cgdir.Context(2 << 30, max_slots=8) as ctx:
+        say("mixed: alone")
+        alone = [ctx.register(*it, prm=pr).cpu().numpy() for it, pr in zip(items, prms)]
+        say("mixed: batch")
+        outs = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
+        rc, st = ctx.register_batch(items, prms, outs)
+        assert rc == cgdir.OK and st == [cgdir.OK] * len(pairs)
+        for i, (a, o) in enumerate(zip(alone, outs)):
+            np.testing.assert_array_equal(a, o.cpu().numpy(), err_msg="batched pair %d" % i)
+        say("mixed: served")
+        outs = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
+        tickets = [ctx.submit(*it, pr, o) for it, pr, o in zip(items, prms, outs)]
+        for t in tickets:
+            assert ctx.wait(t, int(60e9)) == cgdir.OK
+        for i, (a, o) in enumerate(zip(alone, outs)):
+            np.testing.assert_array_equal(a, o.cpu().numpy(), err_msg="served pair %d" % i)

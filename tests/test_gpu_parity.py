@@ -197,9 +197,10 @@ def test_restrict_and_prolong_through_schedule(ctx, orc):
     assert np.abs(ug - uo).max() <= STEP_TOL * 2  # prolongation doubles the coarse field
 
 
-@pytest.mark.parametrize("levels,mask,it", [(2, 2, (0, 1)), (3, 4, (0, 0, 1)), (3, 6, (0, 1, 1))],
-                         ids=["L2 coarse", "L3 coarsest", "L3 both coarse"])
-def test_contour_terms_at_coarse_levels_schedule(ctx, orc, levels, mask, it):
+@pytest.mark.parametrize("levels,mask,it,spacing", [(2, 2, (0, 1), None), (3, 4, (0, 0, 1), None),
+                                                    (3, 6, (0, 1, 1), None), (2, 3, (0, 1), (1.2, 1.2, 3.0))],
+                         ids=["L2 coarse", "L3 coarsest", "L3 both coarse", "L2 coarse mm"])
+def test_contour_terms_at_coarse_levels_schedule(ctx, orc, levels, mask, it, spacing):
     """Contour terms below the finest level (masks taken at the voxels the restriction
     keeps): with single iterations at coarse levels and none at the finest, the output is
     those iterations prolongated, at 1e-4 per doubling.  Ragged dims exercise the ceil(n/2)
@@ -211,13 +212,14 @@ def test_contour_terms_at_coarse_levels_schedule(ctx, orc, levels, mask, it):
     pair.target_masks = np.stack([pair.target_masks[0], grow(pair.target_masks[0]), pair.target_masks[2]])
     pair.moving_masks = np.stack([pair.moving_masks[0], grow(pair.moving_masks[0]), pair.moving_masks[2]])
     lam = [float(v) for v in rng.uniform(1e-3, 5e-3, 3)]
-    prm = cgdir.params_for_pair(pair, iters=it, contour_level_mask=mask, lambdas=lam)
-    say("coarse contour schedule levels=%d mask=%d" % (levels, mask))
+    extra = {} if spacing is None else dict(spacing=spacing, sigma_fluid=1.5, sigma_diff=1.5)
+    prm = cgdir.params_for_pair(pair, iters=it, contour_level_mask=mask, lambdas=lam, **extra)
+    say("coarse contour schedule levels=%d mask=%d spacing=%s" % (levels, mask, spacing))
     ug = gpu_register(ctx, pair, prm)
     uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
-                            orc.params_for(pair, iters=it, contour_level_mask=mask, lambdas=lam))
+                            orc.params_for(pair, iters=it, contour_level_mask=mask, lambdas=lam, **extra))
     u0, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
-                            orc.params_for(pair, iters=it, contour_level_mask=0, lambdas=lam))
+                            orc.params_for(pair, iters=it, contour_level_mask=0, lambdas=lam, **extra))
     assert np.abs(uo - u0).max() > 1e-3         # the contour terms act at that level
     err = np.abs(ug - uo).max()
     say("  max err %.3g" % err)

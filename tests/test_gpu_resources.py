@@ -1,7 +1,7 @@
 """Every entry point returns what it takes from the context's pool: with a pool of one
 registration's footprint plus the same again, thirty rounds of every call that uses the pool
 (blocking registration from device and host buffers, warp of host buffers, evaluation,
-batched and served registration) all succeed and give the same field each round."""
+batched registration, served registration from device and from host buffers) all succeed and give the same field each round."""
 import numpy as np
 import pytest
 
@@ -46,3 +46,8 @@ def test_pool_is_returned_by_every_call():
             tk = ctx.submit(t, m, tm, mm, prm, o)
             assert ctx.wait(tk, int(60e9)) == cgdir.OK, rnd
             np.testing.assert_array_equal(o.cpu().numpy(), ref)
+            oh = torch.empty((3,) + pair.target.shape)   # served from and to host memory
+            tk = ctx.submit(host(pair.target), host(pair.moving), host(pair.target_masks),
+                            host(pair.moving_masks), prm, oh)
+            assert ctx.wait(tk, int(60e9)) == cgdir.OK, rnd
+            np.testing.assert_array_equal(oh.numpy(), ref)

@@ -7,6 +7,8 @@
 // whether a pair runs alone or batched.
 #include <math.h>
 
+#include <type_traits>
+
 #include "cgdir_internal.h"
 
 namespace cgdir {
@@ -539,8 +541,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     constexpr int CELLS = HT * WD, NP = (CELLS + NT - 1) / NT;
     constexpr int WW = WD + 2, WH = HT + 2, WCELLS = WW * WH, NW = (WCELLS + NT - 1) / NT;
     constexpr int UW = kTileX + 2, UH = TY + 2, UCELLS = UW * UH, NU = (UCELLS + NT - 1) / NT;
+    // The structure bits of the staged planes are kept as 32-bit words, which the force reads
+    // faster than bytes, wherever the block's LDS still fits in 160 KiB with them (bytes for
+    // the widest radii of the 16-row tiles).
+    constexpr int kLdsFloats = 4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + 9 * UCELLS + TY * kTileX;
+    using FrT = typename std::conditional<(4 * kLdsFloats + 16 * WCELLS <= 160 * 1024), uint32_t, uint8_t>::type;
     __shared__ float Wr[4][WCELLS];    // I0~ planes, slot = plane & 3
-    __shared__ uint8_t Fr[4][WCELLS];  // their stencil structure bits
+    __shared__ FrT Fr[4][WCELLS];      // their stencil structure bits
     __shared__ float raw[3][HT][WD];   // du on the tile + R halo
     __shared__ float xs[3][HT][kTileX];
     __shared__ float Us[3][3][UCELLS];  // u planes z-1..z+1, slot (p - z0 + 1) % 3
@@ -588,7 +595,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             const int c = tid + j * NT;
             if (c < WCELLS) {
                 Wr[sl][c] = pw[j];
-                Fr[sl][c] = (uint8_t)pf[j];
+                Fr[sl][c] = (FrT)pf[j];
             }
         }
     };

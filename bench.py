@@ -211,13 +211,23 @@ def evaluated(cgdir, torch, pair, pool):
             t0 = time.perf_counter()
             r = ctx.evaluate(t, m, tm, mm, u)
             ms = (time.perf_counter() - t0) * 1e3
+            # one finest-level iteration: (150 iterations - 50 iterations) / 100, set-up cancelled
+            fin = []
+            for n in (50, 150, 50, 150):
+                pf = cgdir.params_for_pair(pair, levels=1, iters=(n,), contour_level_mask=mask & 1)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                ctx.register(t, m, tm, mm, pf)
+                torch.cuda.synchronize()
+                fin.append((time.perf_counter() - t1) * 1e3)
+            iter_ms = ((fin[1] - fin[0]) + (fin[3] - fin[2])) / 200.0
             st = r["structures"]
             out[name] = {"rms_id": r["whole"]["rms_id"], "cc": r["whole"]["cc"],
                          "rms_id_uroi": r["uroi"]["rms_id"], "cc_uroi": r["uroi"]["cc"],
                          "dsc": [round(x["dsc"], 4) for x in st],
                          "ssd_mean_mm": [round(x["ssd"]["mean"], 3) for x in st],
                          "ssd_p95_mm": [round(x["ssd"]["p95"], 3) for x in st],
-                         "register_ms": reg_ms, "evaluate_ms": ms}
+                         "register_ms": reg_ms, "evaluate_ms": ms, "finest_iteration_ms": iter_ms}
         # before registration
         z = torch.zeros((3,) + tuple(pair.target.shape), device=dev)
         r = ctx.evaluate(t, m, tm, mm, z)

@@ -94,6 +94,26 @@ def test_teacher_forced_step(ctx, orc, name, kw, k, sigma, famp):
     assert err <= STEP_TOL
 
 
+@pytest.mark.parametrize("n", [0, 1, 10, 50, 99])
+def test_teacher_forced_step_along_the_oracle_trajectory(ctx, orc, n):
+    """Config 1 (64x64x32, k = 1, 100 iterations): the oracle's own field after n iterations,
+    rounded to FP32, is the start of one GPU iteration and of one FP64 oracle iteration; they
+    agree to 1e-4 voxel at every n, from the first iteration to the last."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair()
+    un, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, iters=(n,)))
+    u0 = un.astype(np.float32)
+    prm = cgdir.params_for_pair(pair, iters=(1,))
+    say("trajectory step from oracle iteration %d" % n)
+    ug = gpu_register(ctx, pair, prm, initial=u0)
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, iters=(1,)), initial_u=u0.astype(np.float64))
+    err = np.abs(ug - uo).max()
+    say("  max |u| %.3g, step up to %.3g, max err %.3g" % (np.abs(uo).max(), np.abs(uo - u0).max(), err))
+    assert err <= STEP_TOL
+
+
 def test_step_with_different_sigmas(ctx, orc):
     from paper_1301_0970_amd import cgdir
     pair = P.head_neck_pair(dims=(100, 90, 30), amp=4.0, k=2)

@@ -241,6 +241,23 @@ typedef struct cgdir_kernel_stat {
 } cgdir_kernel_stat;
 int cgdir_kernel_stats(cgdir_ctx *ctx, cgdir_kernel_stat *out, int cap, int reset);
 
+/* Tile-shape tuning (the batching of many pairs, one launch per phase, with tile shapes the
+ * context picks by timing candidates on their first launches).  A tuning group is one kernel
+ * (step or smoothing), its Gaussian radius, the dims of the largest pair in the launch and
+ * log2 of the launch's voxel count; results never depend on the shape chosen.
+ *
+ * cgdir_tuning_export writes the groups that have settled as text, one line per group,
+ * "<group> <rows per tile> <planes per tile>\n", NUL-terminated, into buf (cap bytes) and
+ * sets *len to the bytes needed including the NUL; buf may be NULL (cap 0) to ask for *len.
+ * CGDIR_E_INVAL if cap is too small (nothing written) or len is NULL.
+ *
+ * cgdir_tuning_import settles groups from such text (for example one exported by an earlier
+ * process on the same GPU), so that their launches use those shapes without timing any
+ * candidate; later imports of a group replace earlier ones.  CGDIR_E_INVAL, with nothing
+ * imported, if a line is malformed or names a shape that is not a candidate of its kernel. */
+int cgdir_tuning_export(cgdir_ctx *ctx, char *buf, size_t cap, size_t *len);
+int cgdir_tuning_import(cgdir_ctx *ctx, const char *text);
+
 /* ---- evaluation of a registration result (section 2.3) ----------------------------------
  * The paper assesses a field three ways, all computed here on the device:
  *  - intensity: RMS-ID = sqrt(mean((I0~ - T0)^2)) and Pearson's correlation coefficient CC

@@ -7,7 +7,8 @@ raises (there is no fallback implementation).
 
 Names mirror the C entry points: ``create``, ``destroy``, ``register``, ``warp``,
 ``register_batch``, ``submit``, ``poll``, ``cancel``, ``wait``, ``footprint``,
-``strerror``, ``params_default``, ``kernel_stats``, ``evaluate``.  :class:`Context` wraps them for
+``strerror``, ``params_default``, ``kernel_stats``, ``evaluate``, ``tuning_export``,
+``tuning_import``.  :class:`Context` wraps them for
 torch tensors.
 """
 from __future__ import annotations
@@ -98,7 +99,7 @@ class kernel_stat(ctypes.Structure):
 SYMBOLS = ["cgdir_params_default", "cgdir_create", "cgdir_destroy", "cgdir_register",
            "cgdir_warp", "cgdir_register_batch", "cgdir_submit", "cgdir_poll", "cgdir_cancel",
            "cgdir_wait", "cgdir_footprint", "cgdir_strerror", "cgdir_kernel_stats",
-           "cgdir_eval_params_default", "cgdir_evaluate"]
+           "cgdir_eval_params_default", "cgdir_evaluate", "cgdir_tuning_export", "cgdir_tuning_import"]
 
 
 class eval_params(ctypes.Structure):
@@ -152,6 +153,8 @@ def _load():
     lib.cgdir_eval_params_default.restype = None
     lib.cgdir_evaluate.argtypes = [ctypes.c_void_p, P(volume), P(volume), P(masks), P(masks),
                                    ctypes.c_void_p, ctypes.c_int, P(eval_params), P(eval_result)]
+    lib.cgdir_tuning_export.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_size_t)]
+    lib.cgdir_tuning_import.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
     for name in SYMBOLS:
         if name not in ("cgdir_params_default", "cgdir_footprint", "cgdir_strerror",
                         "cgdir_eval_params_default"):
@@ -225,6 +228,18 @@ def cancel(h, ticket: int) -> int:
 
 def wait(h, ticket: int, timeout_ns: int = -1) -> int:
     return LIB.cgdir_wait(h, ctypes.c_uint64(ticket), ctypes.c_int64(timeout_ns))
+
+
+def tuning_export(h) -> str:
+    n = ctypes.c_size_t(0)
+    _check(LIB.cgdir_tuning_export(h, None, 0, ctypes.byref(n)), "cgdir_tuning_export")
+    buf = ctypes.create_string_buffer(n.value)
+    _check(LIB.cgdir_tuning_export(h, buf, n.value, ctypes.byref(n)), "cgdir_tuning_export")
+    return buf.value.decode()
+
+
+def tuning_import(h, text: str) -> int:
+    return LIB.cgdir_tuning_import(h, text.encode())
 
 
 def kernel_stats(h, reset: bool = False) -> List[dict]:
@@ -480,6 +495,14 @@ class Context:
 
     def kernel_stats(self, reset=False):
         return kernel_stats(self.handle, reset)
+
+    def tuning_export(self) -> str:
+        """The settled tile-shape groups as text (see cgdir_tuning_export)."""
+        return tuning_export(self.handle)
+
+    def tuning_import(self, text: str):
+        """Settle tile-shape groups from text an earlier context exported."""
+        _check(tuning_import(self.handle, text), "cgdir_tuning_import")
 
 
 def params_for_pair(pair, **over) -> params:

@@ -225,27 +225,43 @@ class Tuner {
         if (!enabled) return step ? fixed_step : fixed_smooth;
         Entry &e = table_[key];
         if (e.ms.empty()) e.ms.assign(nc, -1.f);
-        if (e.best >= 0) return c[e.best];
-        poll(e);
-        bool all = true;
-        for (float m : e.ms) all = all && m >= 0.f;
-        if (all) {
-            e.best = 0;
-            for (int i = 1; i < nc; ++i)
-                if (e.ms[i] < e.ms[e.best]) e.best = i;
-            if (log) {
-                std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.5f ms per Mvoxel) |", key.c_str(), c[e.best].ty,
-                             c[e.best].tz, e.ms[e.best]);
-                for (int i = 0; i < nc; ++i) std::fprintf(stderr, " %d,%d:%.5f", c[i].ty, c[i].tz, e.ms[i]);
-                std::fprintf(stderr, "\n");
-            }
-            return c[e.best];
-        }
+        if (settle_if_measured(key, e)) return c[e.best];
         if (e.next < nc) {
             *measure = e.next;
             return c[e.next++];
         }
         return c[0];
+    }
+    // settled groups as "<group> <ty> <tz>" lines (groups whose candidates have all been
+    // timed settle here too)
+    std::string export_text()
+    {
+        std::string out;
+        for (auto &kv : table_) {
+            if (!settle_if_measured(kv.first, kv.second)) continue;
+            const TileCfg &c = (kv.first[0] == 'U' ? kStepCands : kSmoothCands)[kv.second.best];
+            out += kv.first + ' ' + std::to_string(c.ty) + ' ' + std::to_string(c.tz) + '\n';
+        }
+        return out;
+    }
+    // the candidate index of shape (ty, tz) for a group's kernel, or -1
+    static int candidate(const std::string &key, int ty, int tz)
+    {
+        if (key.empty() || (key[0] != 'U' && key[0] != 'S')) return -1;
+        const bool step = key[0] == 'U';
+        const TileCfg *c = step ? kStepCands : kSmoothCands;
+        const int nc = step ? (int)(sizeof(kStepCands) / sizeof(TileCfg)) : (int)(sizeof(kSmoothCands) / sizeof(TileCfg));
+        for (int i = 0; i < nc; ++i)
+            if (c[i].ty == ty && c[i].tz == tz) return i;
+        return -1;
+    }
+    void settle(const std::string &key, int cand)
+    {
+        Entry &e = table_[key];
+        const int nc = key[0] == 'U' ? (int)(sizeof(kStepCands) / sizeof(TileCfg))
+                                     : (int)(sizeof(kSmoothCands) / sizeof(TileCfg));
+        if (e.ms.empty()) e.ms.assign(nc, -1.f);
+        e.best = cand;
     }
     void record(const std::string &key, int cand, hipEvent_t a, hipEvent_t b, double voxels)
     {
@@ -281,6 +297,30 @@ class Tuner {
         hipEvent_t a, b;
         double scale;  // to ms per million voxels of the launch
     };
+    struct Entry;
+    // true once the group has a shape: imported, or chosen now that every candidate's timing
+    // has landed (the fastest per voxel)
+    bool settle_if_measured(const std::string &key, Entry &e)
+    {
+        if (e.best >= 0) return true;
+        if (e.ms.empty()) return false;
+        poll(e);
+        for (float m : e.ms)
+            if (m < 0.f) return false;
+        const bool step = key[0] == 'U';
+        const TileCfg *c = step ? kStepCands : kSmoothCands;
+        const int nc = (int)e.ms.size();
+        e.best = 0;
+        for (int i = 1; i < nc; ++i)
+            if (e.ms[i] < e.ms[e.best]) e.best = i;
+        if (log) {
+            std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.5f ms per Mvoxel) |", key.c_str(), c[e.best].ty,
+                         c[e.best].tz, e.ms[e.best]);
+            for (int i = 0; i < nc; ++i) std::fprintf(stderr, " %d,%d:%.5f", c[i].ty, c[i].tz, e.ms[i]);
+            std::fprintf(stderr, "\n");
+        }
+        return true;
+    }
     struct Entry {
         int next = 0, best = -1;
         std::vector<float> ms;
@@ -1847,6 +1887,43 @@ int cgdir_wait(cgdir_ctx *c, uint64_t ticket, int64_t timeout_ns)
         return CGDIR_E_TIMEOUT;
     }
     return r->error;
+}
+
+int cgdir_tuning_export(cgdir_ctx *c, char *buf, size_t cap, size_t *len)
+{
+    if (!c || !len || (cap > 0 && !buf)) return CGDIR_E_INVAL;
+    std::string text;
+    {
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        text = c->tuner.export_text();
+    }
+    *len = text.size() + 1;
+    if (cap < *len) return buf ? CGDIR_E_INVAL : CGDIR_OK;
+    std::memcpy(buf, text.c_str(), text.size() + 1);
+    return CGDIR_OK;
+}
+
+int cgdir_tuning_import(cgdir_ctx *c, const char *text)
+{
+    if (!c || !text) return CGDIR_E_INVAL;
+    std::vector<std::pair<std::string, int>> entries;
+    const char *p = text;
+    while (*p) {
+        const char *e = std::strchr(p, '\n');
+        const std::string line(p, e ? (size_t)(e - p) : std::strlen(p));
+        p = e ? e + 1 : p + line.size();
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;  // blank line
+        char key[128];
+        int ty = 0, tz = 0, used = 0;
+        if (std::sscanf(line.c_str(), "%127s %d %d %n", key, &ty, &tz, &used) != 3 || (size_t)used != line.size())
+            return CGDIR_E_INVAL;
+        const int cand = Tuner::candidate(key, ty, tz);
+        if (cand < 0) return CGDIR_E_INVAL;
+        entries.emplace_back(key, cand);
+    }
+    std::lock_guard<std::mutex> lg(c->launch_mu);
+    for (auto &en : entries) c->tuner.settle(en.first, en.second);
+    return CGDIR_OK;
 }
 
 int cgdir_kernel_stats(cgdir_ctx *c, cgdir_kernel_stat *out, int cap, int reset)

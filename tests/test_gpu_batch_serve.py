@@ -320,3 +320,35 @@ def test_mixed_parameters_batched_and_served_equal_alone():
             assert ctx.wait(t, int(60e9)) == cgdir.OK
         for i, (a, o) in enumerate(zip(alone, outs)):
             np.testing.assert_array_equal(a, o.cpu().numpy(), err_msg="served pair %d" % i)
+
+
+def test_tuning_export_and_import():
+    """A context's settled tile-shape groups export as text; a fresh context that imports them
+    launches with those shapes without timing candidates (every group forced to one shape is
+    reported back unchanged after a registration) and gives bitwise the same field."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.head_neck_pair(dims=(80, 64, 36), amp=3.0, k=2, levels=2, iters=24, seed=71)
+    it = _items([pair])[0]
+    prm = cgdir.params_for_pair(pair)
+    with cgdir.Context(1 << 30) as c1:
+        u1 = c1.register(*it, prm=prm).cpu().numpy()
+        text = c1.tuning_export()
+    lines = [l for l in text.splitlines() if l]
+    say("exported %d groups" % len(lines))
+    assert any(l.startswith("U") for l in lines) and any(l.startswith("S") for l in lines)
+    forced = "\n".join("%s 4 8" % l.split()[0] for l in lines) + "\n"
+    with cgdir.Context(1 << 30) as c2:
+        c2.tuning_import(forced)
+        u2 = c2.register(*it, prm=prm).cpu().numpy()
+        back = set(l for l in c2.tuning_export().splitlines() if l)
+    assert set(forced.splitlines()) <= back
+    np.testing.assert_array_equal(u1, u2)
+    with cgdir.Context(1 << 30) as c3:
+        c3.tuning_import("\n" + text + "\n\n")
+        u3 = c3.register(*it, prm=prm).cpu().numpy()
+        assert set(lines) <= set(l for l in c3.tuning_export().splitlines() if l)
+        np.testing.assert_array_equal(u1, u3)
+        for bad in ("U3:8x8x8/9 5 5\n", "X3:8x8x8/9 8 32\n", "U3:8x8x8/9 8\n", "U3:8x8x8/9 8 32 1\n"):
+            with pytest.raises(cgdir.CgdirError) as e:
+                c3.tuning_import(bad)
+            assert e.value.code == cgdir.E_INVAL, bad

@@ -237,6 +237,34 @@ def evaluated(cgdir, torch, pair, pool):
     return out
 
 
+def cold_start(cgdir, torch, pair, pool):
+    """The first registration in a fresh context: with its tile shapes still to be tuned (the
+    first launches of each group try candidate shapes), and with the groups imported from an
+    earlier context's cgdir_tuning_export."""
+    dev = torch.device("cuda")
+    t = torch.from_numpy(pair.target).to(dev)
+    m = torch.from_numpy(pair.moving).to(dev)
+    tm = torch.from_numpy(pair.target_masks).to(dev)
+    mm = torch.from_numpy(pair.moving_masks).to(dev)
+    prm = cgdir.params_for_pair(pair)
+
+    def first(text=None):
+        with cgdir.Context(pool) as ctx:
+            if text is not None:
+                ctx.tuning_import(text)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.register(t, m, tm, mm, prm)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            return ms, ctx.tuning_export()
+    _, text = first()                                   # tunes; module loads happen here
+    untuned, _ = first()
+    imported, _ = first(text)
+    return {"untuned_first_ms": untuned, "imported_first_ms": imported,
+            "groups": len([l for l in text.splitlines() if l])}
+
+
 def warm_start(cgdir, torch, pair, pool, iters=30):
     """Re-registration from an existing field (finest level only, no coarse demons) against
     the full pyramid: latency and the resulting overlap (device evaluation)."""
@@ -319,6 +347,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--warm-start", action="store_true",
                     help="also time a finest-level re-registration started from the full result")
+    ap.add_argument("--cold-start", action="store_true",
+                    help="also time the first registration of a fresh context, untuned and with imported tile shapes")
     ap.add_argument("--evaluate", action="store_true",
                     help="also evaluate (section 2.3 metrics) CG-DIR, CG-DIR with contour terms at every level and plain demons on the workload")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
@@ -421,6 +451,9 @@ def main():
     if args.warm_start:
         log("warm start")
         result["warm_start"] = warm_start(cgdir, torch, pair, pool + (1 << 30))
+    if args.cold_start:
+        log("cold start")
+        result["cold_start"] = cold_start(cgdir, torch, pair, pool + (1 << 30))
     if args.evaluate:
         log("evaluation")
         result["evaluation"] = evaluated(cgdir, torch, pair, pool + (1 << 30))

@@ -803,32 +803,30 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             const Split sx = split_axis(gx, s[0], nx);
             const Split sy = split_axis(gy, s[1], ny);
             const Split sz = split_axis(z, s[2], nz);
-            // corner offsets from the voxel, -1, 0 or +1 when all corners lie in the ring
-            const int ox0 = sx.i0 - gx, ox1 = sx.i1 - gx, oy0 = sy.i0 - gy, oy1 = sy.i1 - gy;
-            const int oz0 = sz.i0 - z, oz1 = sz.i1 - z;
-            const bool near = ox0 >= -1 && ox1 <= 1 && oy0 >= -1 && oy1 <= 1 && oz0 >= -1 && oz1 <= 1;
-            if (near) {  // all corners in the staged planes
+            // lower corner offsets from the voxel; with each in {-1, 0} all corners lie in the
+            // ring.  The ring holds a one-cell halo staged at clamped coordinates, so the upper
+            // corner along each axis is the next column, row or plane of the ring even where
+            // the sample index was clamped (it holds the same value).
+            const int ox0 = sx.i0 - gx, oy0 = sy.i0 - gy, oz0 = sz.i0 - z;
+            const bool near = ox0 >= -1 && ox0 <= 0 && oy0 >= -1 && oy0 <= 0 && oz0 >= -1 && oz0 <= 0;
+            if (near) {
                 // ring cells: the plane's slot base (uniform), the row and the column
                 const int zs_m = ((z - z0) % 3) * UCELLS, zs_0 = ((z - z0 + 1) % 3) * UCELLS;
                 const int zs_p = ((z - z0 + 2) % 3) * UCELLS;
-                const int b0 = oz0 < 0 ? zs_m : (oz0 == 0 ? zs_0 : zs_p);
-                const int b1 = oz1 < 0 ? zs_m : (oz1 == 0 ? zs_0 : zs_p);
-                const int own_c = (ty + 1) * UW + tx + 1;
-                const int r0 = own_c + (oy0 < 0 ? -UW : (oy0 > 0 ? UW : 0));
-                const int r1 = own_c + (oy1 < 0 ? -UW : (oy1 > 0 ? UW : 0));
-                const int i00 = b0 + r0, i01 = b0 + r1, i10 = b1 + r0, i11 = b1 + r1;
+                const int cell = (ty + 1 + oy0) * UW + tx + 1 + ox0;
+                const int i0 = (oz0 < 0 ? zs_m : zs_0) + cell, i1 = (oz0 < 0 ? zs_0 : zs_p) + cell;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const float *U = &Us[k][0][0];
                     float f[8];
-                    f[0] = U[i00 + ox0];
-                    f[1] = U[i00 + ox1];
-                    f[2] = U[i01 + ox0];
-                    f[3] = U[i01 + ox1];
-                    f[4] = U[i10 + ox0];
-                    f[5] = U[i10 + ox1];
-                    f[6] = U[i11 + ox0];
-                    f[7] = U[i11 + ox1];
+                    f[0] = U[i0];
+                    f[1] = U[i0 + 1];
+                    f[2] = U[i0 + UW];
+                    f[3] = U[i0 + UW + 1];
+                    f[4] = U[i1];
+                    f[5] = U[i1 + 1];
+                    f[6] = U[i1 + UW];
+                    f[7] = U[i1 + UW + 1];
                     stg(a.uc[k], v, s[k] + lerp8(f, sx.t, sy.t, sz.t));
                 }
             } else {

@@ -242,10 +242,15 @@ __device__ __forceinline__ void warp_finish(const WarpArgs &w, const WarpPending
 // cells comes from the warp; where several do, K_i~ is re-evaluated from the field.
 //
 // w: I0~ at the voxel and its six clamped neighbours (centre, -x, +x, -y, +y, -z, +z);
-// f: their stencil structure bits (zero when the level has no contour terms).
+// f: their stencil structure bits (zero when the level has no contour terms);
+// kl, ks: K~ staged in LDS: the centre of plane slot s at kl[ks[s]] (s: 0 this plane, 1 the
+// one below, 2 the one above; rows kRow apart), read only where f[q] is nonzero; without
+// staging (kLds false) K~ is read from memory.
 // ============================================================================
+template <bool kLds, int kRow>
 __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], const uint32_t f[7], float t0,
-                                         uint32_t tb, int gx, int gy, int gz, float du[3], float *dout)
+                                         uint32_t tb, int gx, int gy, int gz, const float *kl, const int ks[3],
+                                         float du[3], float *dout)
 {
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
     const float g0x = a.gs[0] * (w[2] - w[1]);
@@ -273,23 +278,47 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
             // one structure i near: K_i~ at each stencil cell from the warp (0 where the
             // cell's corners miss the structure)
             const int i = __builtin_ctz(kb);
-            const float *__restrict__ K = a.K;
-            const int v = gx + nx * gy + nxy * gz;
-            const float Kc = f[0] ? ldg(K, v) : 0.f;
-            const float gkx = a.gs[0] * ((f[2] ? ldg(K, xp + nx * gy + nxy * gz) : 0.f) - (f[1] ? ldg(K, xm + nx * gy + nxy * gz) : 0.f));
-            const float gky = a.gs[0] * ((f[4] ? ldg(K, gx + nx * yp + nxy * gz) : 0.f) - (f[3] ? ldg(K, gx + nx * ym + nxy * gz) : 0.f));
-            const float gkz = a.gs[1] * ((f[6] ? ldg(K, gx + nx * gy + nxy * zp) : 0.f) - (f[5] ? ldg(K, gx + nx * gy + nxy * zm) : 0.f));
+            float Kq[7];
+            if constexpr (kLds) {
+                const float *k0 = kl + ks[0];
+                Kq[0] = f[0] ? k0[0] : 0.f;
+                Kq[1] = f[1] ? k0[-1] : 0.f;
+                Kq[2] = f[2] ? k0[1] : 0.f;
+                Kq[3] = f[3] ? k0[-kRow] : 0.f;
+                Kq[4] = f[4] ? k0[kRow] : 0.f;
+                Kq[5] = f[5] ? kl[ks[1]] : 0.f;
+                Kq[6] = f[6] ? kl[ks[2]] : 0.f;
+            } else {
+                const float *__restrict__ K = a.K;
+                const int v = gx + nx * gy + nxy * gz;
+                Kq[0] = f[0] ? ldg(K, v) : 0.f;
+                Kq[1] = f[1] ? ldg(K, xm + nx * gy + nxy * gz) : 0.f;
+                Kq[2] = f[2] ? ldg(K, xp + nx * gy + nxy * gz) : 0.f;
+                Kq[3] = f[3] ? ldg(K, gx + nx * ym + nxy * gz) : 0.f;
+                Kq[4] = f[4] ? ldg(K, gx + nx * yp + nxy * gz) : 0.f;
+                Kq[5] = f[5] ? ldg(K, gx + nx * gy + nxy * zm) : 0.f;
+                Kq[6] = f[6] ? ldg(K, gx + nx * gy + nxy * zp) : 0.f;
+            }
+            const float Kc = Kq[0];
+            const float gkx = a.gs[0] * (Kq[2] - Kq[1]);
+            const float gky = a.gs[0] * (Kq[4] - Kq[3]);
+            const float gkz = a.gs[1] * (Kq[6] - Kq[5]);
             const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
             const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
             const float ai = __builtin_fmaf(hs, proj, a0);
             const float ni = (tb & kb) ? t0 + a.c0 : 0.f;
             const float di = __builtin_fmaf(hs, ni - Kc, d);
-            const float la = a.lam[i] * ai;
+            float lam_i = 0.f;
+            lam_off = 0.f;
+#pragma unroll
+            for (int j = 0; j < kMaxStructs; ++j) {
+                const float lj = a.lam[j];
+                lam_i = j == i ? lj : lam_i;
+                lam_off += j == i ? 0.f : lj;
+            }
+            const float la = lam_i * ai;
             num = __builtin_fmaf(la, di, num);
             den = __builtin_fmaf(la, ai, den);
-            lam_off = 0.f;
-            for (int j = 0; j < a.k; ++j)
-                if (j != i) lam_off += a.lam[j];
         } else {  // several structures near: their terms in full
             lam_off = 0.f;
             const float tc0 = t0 + a.c0;
@@ -541,13 +570,21 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     constexpr int CELLS = HT * WD, NP = (CELLS + NT - 1) / NT;
     constexpr int WW = WD + 2, WH = HT + 2, WCELLS = WW * WH, NW = (WCELLS + NT - 1) / NT;
     constexpr int UW = kTileX + 2, UH = TY + 2, UCELLS = UW * UH, NU = (UCELLS + NT - 1) / NT;
-    // The structure bits of the staged planes are kept as 32-bit words, which the force reads
-    // faster than bytes, wherever the block's LDS still fits in 160 KiB with them (bytes for
-    // the widest radii of the 16-row tiles).
-    constexpr int kLdsFloats = 4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + 9 * UCELLS + TY * kTileX;
-    using FrT = typename std::conditional<(4 * kLdsFloats + 16 * WCELLS <= 160 * 1024), uint32_t, uint8_t>::type;
+    // LDS of the block (160 KiB at most): the structure bits as 32-bit words, which the force
+    // reads faster than bytes (bytes for the widest radii), and, where the words leave room,
+    // for the 16-row tiles (one block per CU: the slowest block sets the launch's time) K~
+    // of three staged planes (the warped masked moving image of the one structure near a
+    // cell), so that the force near a structure reads no memory.  (Smaller tiles keep their
+    // LDS small so that more blocks share a CU.)
+    constexpr int kLdsBase = 4 * (4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + 9 * UCELLS + TY * kTileX);
+    constexpr int kLdsMax = 160 * 1024, kKrBytes = 12 * WCELLS;
+    constexpr bool kFr32 = kLdsBase + 16 * WCELLS <= kLdsMax;
+    constexpr bool kStageK = TY == 16 && kLdsBase + 16 * WCELLS + kKrBytes <= kLdsMax;
+    using FrT = typename std::conditional<kFr32, uint32_t, uint8_t>::type;
     __shared__ float Wr[4][WCELLS];    // I0~ planes, slot = plane & 3
     __shared__ FrT Fr[4][WCELLS];      // their stencil structure bits
+    __shared__ float Kr[kStageK ? 3 : 1][kStageK ? WCELLS : 1];  // K~ where the bits are nonzero,
+                                                                 // slot = plane % 3
     __shared__ float raw[3][HT][WD];   // du on the tile + R halo
     __shared__ float xs[3][HT][kTileX];
     __shared__ float Us[3][3][UCELLS];  // u planes z-1..z+1, slot (p - z0 + 1) % 3
@@ -588,6 +625,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                 pf[j] = masked ? ldg(a.F, base + woff[j]) : 0u;
             }
     };
+    // w_store also issues the K~ loads of the cells whose bits are nonzero; k_store puts them
+    // into the K~ ring once the plane they replace is no longer read (after the next force
+    // pass) and their latency is covered
+    float pk[NW];
+    uint32_t kpend = 0u;
+    int kplane = 0;
+    bool kwave = false;  // this wave has K~ loads pending
     auto w_store = [&](int p) {
         const int sl = p & 3;
 #pragma unroll
@@ -596,6 +640,36 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             if (c < WCELLS) {
                 Wr[sl][c] = pw[j];
                 Fr[sl][c] = (FrT)pf[j];
+            }
+        }
+        if constexpr (kStageK) {
+            kpend = 0u;
+            kplane = p;
+            uint32_t any = 0u;
+#pragma unroll
+            for (int j = 0; j < NW; ++j)
+                if (tid + j * NT < WCELLS) any |= pf[j];
+            kwave = masked && __ballot(any != 0u) != 0ull;  // (the same in every lane)
+            if (kwave) {
+                const int base = nxy * p;
+#pragma unroll
+                for (int j = 0; j < NW; ++j)
+                    if (tid + j * NT < WCELLS && pf[j] != 0) {
+                        pk[j] = ldg(a.K, base + woff[j]);
+                        kpend |= 1u << j;
+                    }
+            }
+        }
+    };
+    auto k_store = [&]() {
+        if constexpr (kStageK) {
+            if (kwave) {
+                const int sl = kplane % 3;
+#pragma unroll
+                for (int j = 0; j < NW; ++j)
+                    if ((kpend >> j) & 1u) Kr[sl][tid + j * NT] = pk[j];
+                kpend = 0u;
+                kwave = false;
             }
         }
     };
@@ -678,10 +752,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int pa = max(zs, 0), pb = min(ze, nz - 1);
     w_load(max(pa - 1, 0));
     w_store(max(pa - 1, 0));
+    k_store();
     w_load(pa);
     w_store(pa);
+    k_store();
     w_load(min(pa + 1, nz - 1));
     w_store(min(pa + 1, nz - 1));
+    k_store();
     w_load(min(pa + 2, nz - 1));
     t_load(pa);
     u_load(z0 - 1);
@@ -704,6 +781,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
         if (pc != prev) {
             // ---- du on plane pc, tile + R halo
             const int s0 = pc & 3, sm = max(pc - 1, 0) & 3, sp = min(pc + 1, nz - 1) & 3;
+            const int kslots[3] = {(pc % 3) * WCELLS, (max(pc - 1, 0) % 3) * WCELLS, (min(pc + 1, nz - 1) % 3) * WCELLS};
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
                 const int c = tid + j * NT;
@@ -732,7 +810,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                         for (int q = 0; q < 7; ++q) f7[q] = 0u;
                     }
                     float du[3], d;
-                    force_at(a, w7, f7, pt[j], ptb[j], cx, cy, pc, du, &d);
+                    force_at<kStageK, WW>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, &Kr[0][0] + wo, kslots, du, &d);
                     (&raw[0][0][0])[c] = du[0];  // cell c is row c / WD, column c % WD
                     (&raw[1][0][0])[c] = du[1];
                     (&raw[2][0][0])[c] = du[2];
@@ -769,6 +847,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                 u_store(z + 1);
                 u_load(z + 2);
             }
+            k_store();
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < 3; ++k) {

@@ -243,14 +243,15 @@ __device__ __forceinline__ void warp_finish(const WarpArgs &w, const WarpPending
 //
 // w: I0~ at the voxel and its six clamped neighbours (centre, -x, +x, -y, +y, -z, +z);
 // f: their stencil structure bits (zero when the level has no contour terms);
+// lamt: lambda_i at [i] and the sum of the other weights in index order at [kMaxStructs + i];
 // kl, ks: K~ staged in LDS: the centre of plane slot s at kl[ks[s]] (s: 0 this plane, 1 the
 // one below, 2 the one above; rows kRow apart), read only where f[q] is nonzero; without
 // staging (kLds false) K~ is read from memory.
 // ============================================================================
 template <bool kLds, int kRow>
 __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], const uint32_t f[7], float t0,
-                                         uint32_t tb, int gx, int gy, int gz, const float *kl, const int ks[3],
-                                         float du[3], float *dout)
+                                         uint32_t tb, int gx, int gy, int gz, const float *lamt, const float *kl,
+                                         const int ks[3], float du[3], float *dout)
 {
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
     const float g0x = a.gs[0] * (w[2] - w[1]);
@@ -280,14 +281,12 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
             const int i = __builtin_ctz(kb);
             float Kq[7];
             if constexpr (kLds) {
+                // (read unconditionally, then selected: the ring cells of the stencil always
+                // lie in the block's LDS, and a stale value is never selected)
                 const float *k0 = kl + ks[0];
-                Kq[0] = f[0] ? k0[0] : 0.f;
-                Kq[1] = f[1] ? k0[-1] : 0.f;
-                Kq[2] = f[2] ? k0[1] : 0.f;
-                Kq[3] = f[3] ? k0[-kRow] : 0.f;
-                Kq[4] = f[4] ? k0[kRow] : 0.f;
-                Kq[5] = f[5] ? kl[ks[1]] : 0.f;
-                Kq[6] = f[6] ? kl[ks[2]] : 0.f;
+                const float kv[7] = {k0[0], k0[-1], k0[1], k0[-kRow], k0[kRow], kl[ks[1]], kl[ks[2]]};
+#pragma unroll
+                for (int q = 0; q < 7; ++q) Kq[q] = f[q] ? kv[q] : 0.f;
             } else {
                 const float *__restrict__ K = a.K;
                 const int v = gx + nx * gy + nxy * gz;
@@ -308,15 +307,8 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
             const float ai = __builtin_fmaf(hs, proj, a0);
             const float ni = (tb & kb) ? t0 + a.c0 : 0.f;
             const float di = __builtin_fmaf(hs, ni - Kc, d);
-            float lam_i = 0.f;
-            lam_off = 0.f;
-#pragma unroll
-            for (int j = 0; j < kMaxStructs; ++j) {
-                const float lj = a.lam[j];
-                lam_i = j == i ? lj : lam_i;
-                lam_off += j == i ? 0.f : lj;
-            }
-            const float la = lam_i * ai;
+            const float la = lamt[i] * ai;
+            lam_off = lamt[kMaxStructs + i];
             num = __builtin_fmaf(la, di, num);
             den = __builtin_fmaf(la, ai, den);
         } else {  // several structures near: their terms in full
@@ -589,6 +581,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     __shared__ float xs[3][HT][kTileX];
     __shared__ float Us[3][3][UCELLS];  // u planes z-1..z+1, slot (p - z0 + 1) % 3
     __shared__ float dq[TY][kTileX];   // squared metric terms of the tile's voxels
+    __shared__ float lamt[2][kMaxStructs];  // lambda_i; the sum of the other weights
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
@@ -772,6 +765,17 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int ntx = (nx + kTileX - 1) / kTileX;
     float last[3] = {0.f, 0.f, 0.f};
     int prev = -1;
+    if (tid < kMaxStructs) {  // (the weights past k are zero; adding a zero is exact)
+        float li = 0.f, off = 0.f;
+#pragma unroll
+        for (int m = 0; m < kMaxStructs; ++m) {
+            const float lm = a.lam[m];
+            li = m == tid ? lm : li;
+            off += m == tid ? 0.f : lm;
+        }
+        lamt[0][tid] = li;
+        lamt[1][tid] = off;
+    }
     __syncthreads();
     for (int l = zs; l <= ze; ++l) {
         const int pc = clampi(l, 0, nz - 1);
@@ -810,7 +814,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                         for (int q = 0; q < 7; ++q) f7[q] = 0u;
                     }
                     float du[3], d;
-                    force_at<kStageK, WW>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, &Kr[0][0] + wo, kslots, du, &d);
+                    force_at<kStageK, WW>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, &lamt[0][0], &Kr[0][0] + wo, kslots, du, &d);
                     (&raw[0][0][0])[c] = du[0];  // cell c is row c / WD, column c % WD
                     (&raw[1][0][0])[c] = du[1];
                     (&raw[2][0][0])[c] = du[2];

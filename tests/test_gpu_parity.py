@@ -94,6 +94,37 @@ def test_teacher_forced_step(ctx, orc, name, kw, k, sigma, famp):
     assert err <= STEP_TOL
 
 
+def test_structures_at_every_border_under_every_tile_shape(ctx, orc):
+    """Structures cut by the volume's faces (one around the corner (0, 0, 0), one around the
+    opposite corner, one slab through every plane), so that the step kernel stages structure
+    bits and K~ at clamped planes, rows and columns: one teacher-forced iteration under every
+    tile shape the autotuner tries is bitwise the same field, and within 1e-4 voxel of the
+    FP64 oracle."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.plain_pair(dims=(140, 52, 20), amp=3.0)
+    nx, ny, nz = pair.dims
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+
+    def masks(d):  # d: shift of the moving masks against the target's
+        a = ((x - d) ** 2 + (y - d) ** 2 + (z - d) ** 2 <= 11 ** 2)
+        b = ((x - (nx - 1) + d) ** 2 + (y - (ny - 1)) ** 2 + (z - (nz - 1) + d) ** 2 <= 9 ** 2)
+        c = (np.abs(x - 70 - d) <= 6) & (np.abs(y - 26) <= 8)
+        return np.stack([a, b, c]).astype(np.uint8)
+    pair.target_masks, pair.moving_masks, pair.signs = masks(0), masks(1), (1, -1, 1)
+    u0 = P.random_smooth_field(pair.dims, 2.5, 303)
+    lam, sg = [1e-3, 2e-3, 3e-3], [1, -1, 1]
+    prm = cgdir.make_params(levels=1, iters=(1,), sigma_fluid=1.0, sigma_diff=1.0, lambdas=lam, signs=sg)
+    say("structures at the borders: every tile shape")
+    first = gpu_register(ctx, pair, prm, initial=u0)
+    for i in range(15):               # the autotuner's candidate shapes, then the tuned one
+        again = gpu_register(ctx, pair, prm, initial=u0)
+        assert np.array_equal(first, again), i
+    uo = oracle_step(orc, pair, u0, 1.0, 1.0, lam, sg)
+    err = np.abs(first - uo).max()
+    say("  max |du| %.3g  max err %.3g" % (np.abs(uo - u0).max(), err))
+    assert err <= STEP_TOL
+
+
 @pytest.mark.parametrize("n", [0, 1, 10, 50, 99])
 def test_teacher_forced_step_along_the_oracle_trajectory(ctx, orc, n):
     """Config 1 (64x64x32, k = 1, 100 iterations): the oracle's own field after n iterations,

@@ -785,7 +785,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
         if (pc != prev) {
             // ---- du on plane pc, tile + R halo
             const int s0 = pc & 3, sm = max(pc - 1, 0) & 3, sp = min(pc + 1, nz - 1) & 3;
-            const int kslots[3] = {(pc % 3) * WCELLS, (max(pc - 1, 0) % 3) * WCELLS, (min(pc + 1, nz - 1) % 3) * WCELLS};
+            // K~ ring slots of this plane and the ones below and above (slot = plane % 3)
+            const int kslots[3] = {(pc % 3) * WCELLS, (max(pc - 1, 0) % 3) * WCELLS,
+                                   (min(pc + 1, nz - 1) % 3) * WCELLS};
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
                 const int c = tid + j * NT;
@@ -814,7 +816,8 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                         for (int q = 0; q < 7; ++q) f7[q] = 0u;
                     }
                     float du[3], d;
-                    force_at<kStageK, WW>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, &lamt[0][0], &Kr[0][0] + wo, kslots, du, &d);
+                    force_at<kStageK, WW>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, &lamt[0][0],
+                                          kStageK ? &Kr[0][0] + wo : nullptr, kslots, du, &d);
                     (&raw[0][0][0])[c] = du[0];  // cell c is row c / WD, column c % WD
                     (&raw[1][0][0])[c] = du[1];
                     (&raw[2][0][0])[c] = du[2];

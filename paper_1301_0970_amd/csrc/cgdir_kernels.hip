@@ -354,12 +354,6 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
     du[2] = vv * nzv * (2.f * a.gs[1]);
 }
 
-// number of tiles (blocks) of a volume for a tile of 64 x TY columns and TZ planes
-__device__ __host__ __forceinline__ int tile_count(const Dims &d, int ty_rows, int tz)
-{
-    return ((d.nx + kTileX - 1) / kTileX) * ((d.ny + ty_rows - 1) / ty_rows) * ((d.nz + tz - 1) / tz);
-}
-
 // pair owning logical block L of a batched launch: prefix[q] <= L < prefix[q + 1]
 __device__ __forceinline__ int pair_of(const int *prefix, int n, int L)
 {

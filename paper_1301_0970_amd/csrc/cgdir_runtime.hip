@@ -160,7 +160,7 @@ Tuning tuning_from_env()
 
 bool want_delta(const cgdir_params &p) { return p.stop_mode != 0 || p.delta_hist != nullptr; }
 
-size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images, const Tuning &t)
+size_t footprint_bytes(Dims d0, int k, const cgdir_params &p, bool host_images)
 {
     const size_t n0 = (size_t)d0.n();
     size_t b = 0;
@@ -282,12 +282,12 @@ class Tuner {
     {
         for (auto &kv : table_)
             for (auto &p : kv.second.pending) {
-                hipEventSynchronize(p.b);
+                (void)hipEventSynchronize(p.b);  // (tear-down: an error leaves nothing to do)
                 spare_.push_back(p.a);
                 spare_.push_back(p.b);
             }
         table_.clear();
-        for (hipEvent_t e : spare_) hipEventDestroy(e);
+        for (hipEvent_t e : spare_) (void)hipEventDestroy(e);
         spare_.clear();
     }
 
@@ -466,14 +466,17 @@ hipError_t timed(cgdir_ctx *c, int slot, double vox, F &&fn)
     if (c->pending.size() > 8192) drain_profile(c);
     hipEvent_t a = take_event(c), b = take_event(c);
     if (!a || !b) return fn();
-    hipEventRecord(a, c->stream);
+    const bool ra = hipEventRecord(a, c->stream) == hipSuccess;
     hipError_t e = fn();
-    hipEventRecord(b, c->stream);
-    c->pending.push_back({slot, a, b, vox});
+    const bool rb = hipEventRecord(b, c->stream) == hipSuccess;
+    if (ra && rb) {
+        c->pending.push_back({slot, a, b, vox});
+    } else {  // (an unrecorded pair is not timed)
+        c->spare_events.push_back(a);
+        c->spare_events.push_back(b);
+    }
     return e;
 }
-
-int hip_code(hipError_t e) { return e == hipSuccess ? CGDIR_OK : CGDIR_E_HIP; }
 
 #define CG_TRY(expr)                          \
     do {                                      \
@@ -617,7 +620,7 @@ struct Job {
     bool finished = false;
     int iters_done0 = 0;
 
-    size_t need() const { return footprint_bytes(d0, k, req.params, host_images, ctx->tune); }
+    size_t need() const { return footprint_bytes(d0, k, req.params, host_images); }
 
     int init(cgdir_ctx *c, const cgdir_request &r)
     {
@@ -673,8 +676,8 @@ struct Job {
         for (void *p : allocs) ctx->pool.release(p);
         allocs.clear();
         if (pin_ev) {
-            if (pin_busy) hipEventSynchronize(pin_ev);  // no copy may land in a recycled record
-            hipEventDestroy(pin_ev);
+            if (pin_busy) (void)hipEventSynchronize(pin_ev);  // no copy may land in a recycled record
+            (void)hipEventDestroy(pin_ev);
             pin_ev = nullptr;
             pin_busy = false;
         }
@@ -1106,9 +1109,10 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
         if (!measure_it) return fn();
         hipEvent_t ea = c->tuner.event(), eb = c->tuner.event();
         if (!ea || !eb) return fn();
-        hipEventRecord(ea, s);
+        // (a pair that failed to record reads as untimeable: the candidate is then never chosen)
+        (void)hipEventRecord(ea, s);
         const hipError_t e = fn();
-        hipEventRecord(eb, s);
+        (void)hipEventRecord(eb, s);
         c->tuner.record(key, cand, ea, eb, voxels);
         return e;
     };
@@ -1213,7 +1217,7 @@ void finish_request(cgdir_ctx *c, cgdir_ctx::Request *r, int code)
 // here belong to this thread alone.
 void scheduler(cgdir_ctx *c)
 {
-    hipSetDevice(c->device);
+    const bool device_ok = hipSetDevice(c->device) == hipSuccess;  // (else every request fails)
     std::vector<hipEvent_t> spare;
     auto get_ev = [&]() -> hipEvent_t {
         if (!spare.empty()) {
@@ -1242,7 +1246,7 @@ void scheduler(cgdir_ctx *c)
                 }
                 if (c->queue.empty() || (int)active.size() >= c->max_slots) break;
                 r = c->reqs.find(c->queue.front())->second.get();
-                const int rc = r->job.allocate();
+                const int rc = device_ok ? r->job.allocate() : CGDIR_E_HIP;
                 if (rc == CGDIR_E_NOMEM) break;  // the head of the queue waits for memory
                 c->queue.pop_front();
                 if (rc != CGDIR_OK) {
@@ -1259,7 +1263,7 @@ void scheduler(cgdir_ctx *c)
                 rc = r->job.setup();
             }
             if (rc != CGDIR_OK) {
-                hipStreamSynchronize(c->stream);  // set-up work in flight may still use its memory
+                (void)hipStreamSynchronize(c->stream);  // set-up work in flight may still use its memory
                 std::lock_guard<std::mutex> lk(c->mu);
                 finish_request(c, r, rc);
                 c->cv.notify_all();
@@ -1296,18 +1300,23 @@ void scheduler(cgdir_ctx *c)
                 if (r->job.finished && !r->emitted) {
                     if (r->error == CGDIR_OK) r->error = r->job.emit();
                     r->done_ev = get_ev();
-                    if (r->done_ev) hipEventRecord(r->done_ev, c->stream);
+                    if (r->done_ev && hipEventRecord(r->done_ev, c->stream) != hipSuccess) {
+                        spare.push_back(r->done_ev);  // (completion then found by a stream sync)
+                        r->done_ev = nullptr;
+                    }
                     r->emitted = true;
                 }
             }
             hipEvent_t te = get_ev();
             if (te) {
-                hipEventRecord(te, c->stream);
-                ticks.push_back(te);
+                if (hipEventRecord(te, c->stream) == hipSuccess) ticks.push_back(te);
+                else spare.push_back(te);
             }
         }
         while (ticks.size() > 2) {  // bounded look-ahead of queued ticks
-            hipEventSynchronize(ticks.front());
+            // (an error here is the device's; the next launches and the completion checks
+            // below report it)
+            (void)hipEventSynchronize(ticks.front());
             spare.push_back(ticks.front());
             ticks.pop_front();
         }
@@ -1318,8 +1327,13 @@ void scheduler(cgdir_ctx *c)
             r->level = r->job.level;
             r->iter = r->job.iter;
             r->last_delta = r->job.last_delta;
-            if (r->emitted && (!r->done_ev || hipEventQuery(r->done_ev) == hipSuccess)) {
-                if (!r->done_ev) hipStreamSynchronize(c->stream);  // no event: wait for its copies
+            const hipError_t q = r->emitted && r->done_ev ? hipEventQuery(r->done_ev) : hipSuccess;
+            if (r->emitted && q != hipErrorNotReady) {
+                // no event: wait for its copies; a failed query or sync (a device error) fails
+                // the request instead of leaving it pending
+                hipError_t e = q;
+                if (!r->done_ev) e = hipStreamSynchronize(c->stream);
+                if (e != hipSuccess && r->error == CGDIR_OK) r->error = CGDIR_E_HIP;
                 const int rc = r->error != CGDIR_OK ? r->error : r->job.conclude();
                 if (r->done_ev) spare.push_back(r->done_ev);
                 r->done_ev = nullptr;
@@ -1332,10 +1346,10 @@ void scheduler(cgdir_ctx *c)
         }
     }
     for (hipEvent_t e : ticks) {
-        hipEventSynchronize(e);
+        (void)hipEventSynchronize(e);
         spare.push_back(e);
     }
-    for (hipEvent_t e : spare) hipEventDestroy(e);
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
 }
 
 }  // namespace
@@ -1399,7 +1413,7 @@ size_t cgdir_footprint(int nx, int ny, int nz, int k, const cgdir_params *params
     }
     if (nx < 1 || ny < 1 || nz < 1 || k < 0 || k > CGDIR_MAX_STRUCTS) return 0;
     if (params->levels < 1 || params->levels > CGDIR_MAX_LEVELS) return 0;
-    return footprint_bytes(Dims{nx, ny, nz}, k, *params, false, Tuning{});
+    return footprint_bytes(Dims{nx, ny, nz}, k, *params, false);
 }
 
 int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
@@ -1428,7 +1442,7 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
     void *pool = desc->pool;
     if (!pool) {
         if (hipMalloc(&c->own_pool, desc->pool_bytes) != hipSuccess) {
-            if (c->own_stream) hipStreamDestroy(c->stream);
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
             return CGDIR_E_NOMEM;
         }
         pool = c->own_pool;
@@ -1441,7 +1455,7 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
 int cgdir_destroy(cgdir_ctx *c)
 {
     if (!c) return CGDIR_E_INVAL;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);  // (tear-down goes on whatever the device's state)
     {
         std::lock_guard<std::mutex> lk(c->mu);
         for (uint64_t t : c->queue) {
@@ -1454,20 +1468,20 @@ int cgdir_destroy(cgdir_ctx *c)
     }
     c->cv.notify_all();
     if (c->sched_started) c->sched.join();
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     {
         std::lock_guard<std::mutex> g(c->prof_mu);
         drain_profile(c);
-        for (hipEvent_t e : c->spare_events) hipEventDestroy(e);
+        for (hipEvent_t e : c->spare_events) (void)hipEventDestroy(e);
         c->spare_events.clear();
     }
     {
         std::lock_guard<std::mutex> lg(c->launch_mu);
         c->tuner.release_all();
     }
-    for (PinRec *chunk : c->pin_chunks) hipHostFree(chunk);
-    if (c->own_pool) hipFree(c->own_pool);
-    if (c->own_stream) hipStreamDestroy(c->stream);
+    for (PinRec *chunk : c->pin_chunks) (void)hipHostFree(chunk);
+    if (c->own_pool) (void)hipFree(c->own_pool);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return CGDIR_OK;
 }
@@ -1486,7 +1500,7 @@ int cgdir_register(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume 
     r.params = *params;
     r.dvf_out = dvf_out;
     r.dvf_where = dvf_where;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return CGDIR_E_HIP;
     Job job;
     CG_TRY(job.init(c, r));
     CG_TRY(job.allocate());
@@ -1512,7 +1526,11 @@ int cgdir_register(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume 
 int cgdir_register_batch(cgdir_ctx *c, int n, const cgdir_request *reqs, int *status)
 {
     if (!c || n < 0 || (n > 0 && !reqs)) return CGDIR_E_INVAL;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) {
+        if (status)
+            for (int i = 0; i < n; ++i) status[i] = CGDIR_E_HIP;
+        return CGDIR_E_HIP;
+    }
     std::vector<std::unique_ptr<Job>> jobs;
     int first = CGDIR_OK;
     std::vector<int> st(n, CGDIR_OK);
@@ -1564,7 +1582,7 @@ int cgdir_warp(cgdir_ctx *c, const cgdir_volume *src, const float *dvf, int mode
         return CGDIR_E_INVAL;
     if (mode != CGDIR_WARP_LINEAR && mode != CGDIR_WARP_MASK) return CGDIR_E_INVAL;
     if (src->where != CGDIR_HOST && src->where != CGDIR_DEVICE) return CGDIR_E_INVAL;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return CGDIR_E_HIP;
     const Dims d{src->nx, src->ny, src->nz};
     const int64_t n = d.n();
     const size_t esz = mode == CGDIR_WARP_LINEAR ? sizeof(float) : 1;
@@ -1682,7 +1700,7 @@ int cgdir_evaluate(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume 
     }
     if (ep->opening_radius < 0 || ep->opening_radius > 16) return CGDIR_E_INVAL;
 
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return CGDIR_E_HIP;
     const Dims d{target->nx, target->ny, target->nz};
     const int64_t n = d.n();
     const hipStream_t s = c->stream;

@@ -18,6 +18,7 @@ Also reported on the same JSON line:
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -117,10 +118,16 @@ def read_traffic(workload, kernel):
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(pair, it=8):
-    """The oracle's Algorithm A on the full-size inputs of the workload, with `it` iterations
-    per level instead of the workload's counts (about 15 s of work on 16 cores)."""
+def cpu_baseline(pair, target_vi=3.0e8):
+    """The oracle's Algorithm A on the full-size inputs of the workload, with the same number
+    of iterations at every level, as many as make about `target_vi` voxel-iterations (8 for
+    the pelvis workload: 10-15 s of work on 16 cores), at most the workload's own count."""
     import oracle
+    per_iter, dims = 0, pair.dims
+    for _ in range(pair.levels):
+        per_iter += dims[0] * dims[1] * dims[2]
+        dims = tuple((n + 1) // 2 for n in dims)
+    it = max(1, min(max(pair.iters), int(math.ceil(target_vi / per_iter))))
     prm = oracle.params_for(pair, iters=(it,) * pair.levels)
     t0 = time.time()
     oracle.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks, prm)

@@ -205,9 +205,9 @@ struct TileCfg {
 };
 // (the small z chunks give coarse pyramid levels enough blocks to fill 256 CUs)
 const TileCfg kStepCands[] = {{8, 32}, {8, 16}, {8, 64}, {8, 128}, {16, 16}, {16, 32}, {16, 64}, {16, 128},
-                              {4, 32}, {4, 128}, {8, 8}, {4, 8}, {4, 16}, {8, 4}, {4, 4}, {8, 2}, {4, 2}};
+                              {4, 32}, {4, 128}, {8, 8}, {4, 8}, {4, 16}, {8, 4}, {4, 4}, {8, 2}, {4, 2}, {8, 1}};
 const TileCfg kSmoothCands[] = {{8, 32}, {8, 8}, {8, 16}, {8, 64}, {8, 128}, {16, 16}, {16, 32}, {16, 64},
-                                {16, 128}, {4, 16}, {4, 64}, {4, 8}, {8, 4}, {4, 4}, {8, 2}, {4, 2}};
+                                {16, 128}, {4, 16}, {4, 64}, {4, 8}, {8, 4}, {4, 4}, {8, 2}, {4, 2}, {8, 1}};
 
 class Tuner {
   public:

@@ -48,7 +48,7 @@ def test_fullsize_step_on_sampled_blocks_and_all_tile_shapes(pelvis, orc):
     with cgdir.Context(4 << 30) as ctx:
         say("full-size step: every tile shape")
         first = ctx.register(t, m, tm, mm, prm, initial=ud).cpu().numpy()
-        for i in range(17):           # the autotuner's candidate shapes, then the tuned one
+        for i in range(18):           # the autotuner's candidate shapes, then the tuned one
             again = ctx.register(t, m, tm, mm, prm, initial=ud).cpu().numpy()
             assert np.array_equal(first, again), i
     nx, ny, nz = pair.dims

@@ -116,7 +116,7 @@ def test_structures_at_every_border_under_every_tile_shape(ctx, orc):
     prm = cgdir.make_params(levels=1, iters=(1,), sigma_fluid=1.0, sigma_diff=1.0, lambdas=lam, signs=sg)
     say("structures at the borders: every tile shape")
     first = gpu_register(ctx, pair, prm, initial=u0)
-    for i in range(17):               # the autotuner's candidate shapes, then the tuned one
+    for i in range(18):               # the autotuner's candidate shapes, then the tuned one
         again = gpu_register(ctx, pair, prm, initial=u0)
         assert np.array_equal(first, again), i
     uo = oracle_step(orc, pair, u0, 1.0, 1.0, lam, sg)

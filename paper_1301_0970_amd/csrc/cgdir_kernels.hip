@@ -549,7 +549,9 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
 // ahead; the field's planes around the output plane (tile + 1 halo) go through a 3-slot
 // ring for the compose gathers, with a global fallback when |s| >= 1.
 // ============================================================================
-template <int R, int TY>
+// kMasked false: no pair of the launch has contour terms at its level (no structure bits, K~
+// or contour weights in LDS, so the block needs less of it and of registers).
+template <int R, int TY, bool kMasked>
 __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
 {
     constexpr int WD = kTileX + 2 * R, HT = TY + 2 * R, NT = kTileX * TY;
@@ -565,10 +567,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     constexpr int kLdsBase = 4 * (4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + 9 * UCELLS + TY * kTileX);
     constexpr int kLdsMax = 160 * 1024, kKrBytes = 12 * WCELLS;
     constexpr bool kFr32 = kLdsBase + 16 * WCELLS <= kLdsMax;
-    constexpr bool kStageK = TY == 16 && kLdsBase + 16 * WCELLS + kKrBytes <= kLdsMax;
+    constexpr bool kStageK = kMasked && TY == 16 && kLdsBase + 16 * WCELLS + kKrBytes <= kLdsMax;
     using FrT = typename std::conditional<kFr32, uint32_t, uint8_t>::type;
     __shared__ float Wr[4][WCELLS];    // I0~ planes, slot = plane & 3
-    __shared__ FrT Fr[4][WCELLS];      // their stencil structure bits
+    __shared__ FrT Fr[kMasked ? 4 : 1][kMasked ? WCELLS : 1];  // their stencil structure bits
     __shared__ float Kr[kStageK ? 3 : 1][kStageK ? WCELLS : 1];  // K~ where the bits are nonzero,
                                                                  // slot = plane % 3
     __shared__ float raw[3][HT][WD];   // du on the tile + R halo
@@ -582,7 +584,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
     const TileCoord tc = tile_of(TY, a.tz, a.d, L);
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
-    const bool masked = a.F != nullptr;
+    const bool masked = kMasked && a.F != nullptr;
     const bool metric = a.partials != nullptr;
     // in-plane (x and y share one voxel size) and z Gaussians
     float wx[R + 1], wz[R + 1];
@@ -626,7 +628,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             const int c = tid + j * NT;
             if (c < WCELLS) {
                 Wr[sl][c] = pw[j];
-                Fr[sl][c] = (FrT)pf[j];
+                if constexpr (kMasked) Fr[sl][c] = (FrT)pf[j];
             }
         }
         if constexpr (kStageK) {
@@ -759,7 +761,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int ntx = (nx + kTileX - 1) / kTileX;
     float last[3] = {0.f, 0.f, 0.f};
     int prev = -1;
-    if (tid < kMaxStructs) {  // (the weights past k are zero; adding a zero is exact)
+    if (kMasked && tid < kMaxStructs) {  // (the weights past k are zero; adding a zero is exact)
         float li = 0.f, off = 0.f;
 #pragma unroll
         for (int m = 0; m < kMaxStructs; ++m) {
@@ -918,7 +920,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     }
 }
 
-template <int R, int TY>
+template <int R, int TY, bool kMasked>
 __global__ void __launch_bounds__(kTileX *TY) k_step_batch(StepBatch b)
 {
     const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
@@ -927,7 +929,7 @@ __global__ void __launch_bounds__(kTileX *TY) k_step_batch(StepBatch b)
         const int s = *b.d[q].stop;
         if (s != 0 && s <= b.d[q].iter) return;
     }
-    step_tile<R, TY>(b.d[q], L - b.prefix[q]);
+    step_tile<R, TY, kMasked>(b.d[q], L - b.prefix[q]);
 }
 
 // Warp of the moving image with the field at the start of a level (the smoothing of u
@@ -1238,19 +1240,19 @@ static int tiles_xy(Dims d, int ty) { return ((d.nx + kTileX - 1) / kTileX) * ((
 
 int tile_blocks(Dims d, int ty, int tz) { return tiles_xy(d, ty) * ((d.nz + tz - 1) / tz); }
 
-// one launch per (radius, tile rows) instantiation
-template <int TY>
+// one launch per (radius, tile rows, contour terms in the launch) instantiation
+template <int TY, bool kMasked>
 static hipError_t step_batch_ty(const StepBatch &b, int radius, hipStream_t s)
 {
     const dim3 grid(b.prefix[b.n]), block(kTileX * TY);
     switch (radius) {
-    case 0: hipLaunchKernelGGL((k_step_batch<0, TY>), grid, block, 0, s, b); break;
-    case 1: hipLaunchKernelGGL((k_step_batch<1, TY>), grid, block, 0, s, b); break;
-    case 2: hipLaunchKernelGGL((k_step_batch<2, TY>), grid, block, 0, s, b); break;
-    case 3: hipLaunchKernelGGL((k_step_batch<3, TY>), grid, block, 0, s, b); break;
-    case 4: hipLaunchKernelGGL((k_step_batch<4, TY>), grid, block, 0, s, b); break;
-    case 5: hipLaunchKernelGGL((k_step_batch<5, TY>), grid, block, 0, s, b); break;
-    case 6: hipLaunchKernelGGL((k_step_batch<6, TY>), grid, block, 0, s, b); break;
+    case 0: hipLaunchKernelGGL((k_step_batch<0, TY, kMasked>), grid, block, 0, s, b); break;
+    case 1: hipLaunchKernelGGL((k_step_batch<1, TY, kMasked>), grid, block, 0, s, b); break;
+    case 2: hipLaunchKernelGGL((k_step_batch<2, TY, kMasked>), grid, block, 0, s, b); break;
+    case 3: hipLaunchKernelGGL((k_step_batch<3, TY, kMasked>), grid, block, 0, s, b); break;
+    case 4: hipLaunchKernelGGL((k_step_batch<4, TY, kMasked>), grid, block, 0, s, b); break;
+    case 5: hipLaunchKernelGGL((k_step_batch<5, TY, kMasked>), grid, block, 0, s, b); break;
+    case 6: hipLaunchKernelGGL((k_step_batch<6, TY, kMasked>), grid, block, 0, s, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1259,10 +1261,12 @@ static hipError_t step_batch_ty(const StepBatch &b, int radius, hipStream_t s)
 hipError_t launch_step_batch(const StepBatch &b, int radius, int ty, hipStream_t s)
 {
     if (b.n < 1 || b.n > kBatchStep || b.prefix[b.n] < 1) return hipErrorInvalidValue;
+    bool masked = false;  // any pair of the launch with contour terms at its level
+    for (int i = 0; i < b.n; ++i) masked = masked || b.d[i].F != nullptr;
     switch (ty) {
-    case 4: return step_batch_ty<4>(b, radius, s);
-    case 8: return step_batch_ty<8>(b, radius, s);
-    case 16: return step_batch_ty<16>(b, radius, s);
+    case 4: return masked ? step_batch_ty<4, true>(b, radius, s) : step_batch_ty<4, false>(b, radius, s);
+    case 8: return masked ? step_batch_ty<8, true>(b, radius, s) : step_batch_ty<8, false>(b, radius, s);
+    case 16: return masked ? step_batch_ty<16, true>(b, radius, s) : step_batch_ty<16, false>(b, radius, s);
     default: return hipErrorInvalidValue;
     }
 }

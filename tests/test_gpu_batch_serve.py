@@ -289,7 +289,9 @@ def test_mixed_parameters_batched_and_served_equal_alone():
     """Pairs whose parameters differ in every way a launch groups by or carries per pair
     (physical spacing with sigma in mm, contour terms at coarse levels, automatic signs, the
     device-side stopping rule, no structures, ragged sizes) give bitwise the same field alone,
-    in one batch and served together."""
+    in one batch and served together.  (Alone, the launches of a level without contour terms
+    take the step kernel's instantiation without them; batched with pairs that have them, the
+    general one: both give the same field.)"""
     import torch
     from paper_1301_0970_amd import cgdir
     pairs = [P.head_neck_pair(dims=(70, 58, 30), amp=3.0, k=3, levels=2, iters=8, seed=61),

@@ -132,7 +132,7 @@ def test_cancel_and_oversize():
 
 
 def test_batch_of_many_small_pairs_spans_several_launches():
-    """More pairs than one launch's descriptor table holds (16 for the step, 20 for the
+    """More pairs than one launch's descriptor table holds (14 for the step, 18 for the
     smoothing): chunked launches, results still equal to each pair alone."""
     import torch
     from paper_1301_0970_amd import cgdir

@@ -177,17 +177,6 @@ def warp_mask(m, u) -> np.ndarray:
     return out
 
 
-def warp_mask_f32(m, u) -> np.ndarray:
-    """Mask warp with the inside decision taken in single precision (FP32 field, fused
-    linear interpolations x then y then z), the precision of the library's mask warp."""
-    m = _u8(m)
-    u = np.ascontiguousarray(u, dtype=np.float32)
-    out = np.empty_like(m)
-    _check(lib().orc_warp_mask_f32(_ptr(m), *_dims(m), u.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
-                                   _ptr(out)), "warp_mask_f32")
-    return out
-
-
 def gradient(f, spacing=None) -> np.ndarray:
     """Central differences (clamped), divided by the voxel size (x, y, z) when given."""
     f = _f64(f)

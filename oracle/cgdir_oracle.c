@@ -163,63 +163,6 @@ int orc_warp_mask(const uint8_t *m, int nx, int ny, int nz, const double *u, uin
     return 0;
 }
 
-/* ---------------------------------------------------------------- mask warp in FP32
- * Whether a propagated voxel is inside a structure is an integer that floating point
- * decides, so this variant takes the decision in single precision, the precision of the
- * library's mask warp: the sample coordinate i + u is split into i + floor(u) and the
- * fraction u - floor(u) (never rounded as a sum), clamped to the volume as in orc_sample,
- * and each linear interpolation a + t (b - a) is one fused rounding, x then y then z. */
-
-static void axis_split_f32(int i, float u, int n, int *i0, int *i1, float *t)
-{
-    const float fu = floorf(u);
-    const float pb = (float)i + fu;
-    const float top = (float)(n - 1);
-    if (pb < 0.f) {
-        *i0 = 0;
-        *t = 0.f;
-    } else if (pb >= top) {
-        *i0 = n - 1;
-        *t = 0.f;
-    } else if (pb != pb) { /* NaN: an in-bounds index and a NaN weight (never inside) */
-        *i0 = 0;
-        *t = u - fu;
-    } else {
-        *i0 = (int)pb;
-        *t = u - fu;
-    }
-    *i1 = *i0 + 1 < n ? *i0 + 1 : n - 1;
-}
-
-static float lerp_f32(float a, float b, float t) { return fmaf(t, b - a, a); }
-
-int orc_warp_mask_f32(const uint8_t *m, int nx, int ny, int nz, const float *u, uint8_t *out)
-{
-    if (bad_dims(nx, ny, nz)) return -1;
-    size_t n = (size_t)nx * ny * nz;
-    const float *ux = u, *uy = u + n, *uz = u + 2 * n;
-#pragma omp parallel for schedule(static)
-    for (int l = 0; l < nz; ++l)
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                size_t v = IDX(i, j, l);
-                int x0, x1, y0, y1, z0, z1;
-                float tx, ty, tz;
-                axis_split_f32(i, ux[v], nx, &x0, &x1, &tx);
-                axis_split_f32(j, uy[v], ny, &y0, &y1, &ty);
-                axis_split_f32(l, uz[v], nz, &z0, &z1, &tz);
-#define MB(a, b, c) (m[IDX(a, b, c)] ? 1.f : 0.f)
-                float c00 = lerp_f32(MB(x0, y0, z0), MB(x1, y0, z0), tx);
-                float c10 = lerp_f32(MB(x0, y1, z0), MB(x1, y1, z0), tx);
-                float c01 = lerp_f32(MB(x0, y0, z1), MB(x1, y0, z1), tx);
-                float c11 = lerp_f32(MB(x0, y1, z1), MB(x1, y1, z1), tx);
-#undef MB
-                float w = lerp_f32(lerp_f32(c00, c10, ty), lerp_f32(c01, c11, ty), tz);
-                out[v] = w >= 0.5f ? 1 : 0;
-            }
-    return 0;
-}
-
 /* ---------------------------------------------------------------- Eq.7 (kernel 3) */
 
 /* v minimising E1(v) of Eq.6 with beta = d^2 (Thirion):

@@ -71,9 +71,6 @@ double orc_sample(const double *f, int nx, int ny, int nz, double px, double py,
 int orc_warp(const double *f, int nx, int ny, int nz, const double *u, double *out);
 /* mask warp: trilinear of the 0/1 mask, inside when >= 0.5 */
 int orc_warp_mask(const uint8_t *m, int nx, int ny, int nz, const double *u, uint8_t *out);
-/* the same decision taken in single precision (FP32 field, fused lerps x then y then z):
-   the precision in which the library decides, for exact comparison of propagated masks */
-int orc_warp_mask_f32(const uint8_t *m, int nx, int ny, int nz, const float *u, uint8_t *out);
 /* Central differences with clamped indices: g = 3 planes. */
 int orc_gradient(const double *f, int nx, int ny, int nz, double *g);
 /* The same divided by the voxel size h[3] of each axis (h NULL: 1). */

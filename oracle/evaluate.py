@@ -17,10 +17,14 @@ What section 2.3 measures, with the readings taken where it is silent:
     reported as mean, standard deviation (population) and 95th percentile (linear
     interpolation between order statistics).
 
-The inside decision of the mask warp is taken in FP32 (``warp_mask_f32``), the library's
-precision; everything else is exact integer work or FP64.  Distances are computed as
-((dx sx)^2 + (dy sy)^2) + (dz sz)^2 in FP64 with dx, dy, dz integer voxel offsets and the
-spacings taken as single-precision values, then the square root of the minimum.
+The mask warp is FP64: the trilinear value of the 0/1 mask at x + u(x), inside when >= 0.5.
+Whether a voxel is inside is an integer that floating point decides, so a voxel whose FP64 value
+lies within KNIFE_EDGE of 0.5 may be decided either way by a correct evaluation in single
+precision; such knife-edge voxels are listed with each structure, and ``flips`` lets a caller
+take their decision the other way, so that every valid result can be enumerated.  Everything
+else is exact integer work or FP64.  Distances are computed as ((dx sx)^2 + (dy sy)^2) +
+(dz sz)^2 in FP64 with dx, dy, dz integer voxel offsets and the spacings taken as
+single-precision values, then the square root of the minimum.
 """
 from __future__ import annotations
 
@@ -28,9 +32,14 @@ import numpy as np
 
 from . import uroi as _uroi
 from . import warp as _warp
-from . import warp_mask_f32 as _warp_mask_f32
 
 DEFAULT_SPACING = (1.97, 1.97, 2.5)     # mm along x, y, z (section 2.3)
+
+# Bound on |v32 - v64| for the trilinear value v of a 0/1 mask evaluated in single precision
+# from the same float32 field: the fraction of each coordinate is exact or off by one rounding
+# (2^-24), and each of the seven linear interpolations of values in [0, 1] adds at most one
+# rounding, so |v32 - v64| < 1e-6; the margin is four times that.
+KNIFE_EDGE = 4e-6
 
 
 def _neighbour(m: np.ndarray, axis: int, step: int) -> np.ndarray:
@@ -136,9 +145,30 @@ def rms_cc(a: np.ndarray, b: np.ndarray, region=None) -> dict:
     return {"rms_id": rms, "cc": cc, "voxels": int(a.size)}
 
 
+def deformed_mask(mask: np.ndarray, u) -> tuple:
+    """The structure propagated by the field (FP64 mask warp): the inside decision per voxel and
+    the knife-edge voxels (flat x-fastest indices) whose trilinear value lies within KNIFE_EDGE
+    of 0.5."""
+    u64 = np.ascontiguousarray(u, dtype=np.float32).astype(np.float64)
+    v = _warp(np.asarray(mask, dtype=bool).astype(np.float64), u64)
+    return v >= 0.5, np.flatnonzero(np.abs(v - 0.5) <= KNIFE_EDGE)
+
+
+def structure(deformed: np.ndarray, target: np.ndarray, spacing=DEFAULT_SPACING, radius: int = 1) -> dict:
+    """Overlap and contour metrics of one deformed structure against its target mask."""
+    d = deformed.astype(bool)
+    t = target.astype(bool)
+    rec = dsc(d, t)
+    contour = boundary(opening(d, radius))
+    rec["ssd"] = distance_stats(surface_distances(contour, boundary(t), spacing))
+    return rec
+
+
 def evaluate(target, moving, target_masks, moving_masks, u, spacing=DEFAULT_SPACING,
-             radius: int = 1, margin=(5, 5, 4)) -> dict:
-    """All section 2.3 metrics of the field u (3, nz, ny, nx) registering moving to target."""
+             radius: int = 1, margin=(5, 5, 4), flips=None) -> dict:
+    """All section 2.3 metrics of the field u (3, nz, ny, nx) registering moving to target.
+    flips: optional, one sequence per structure of knife-edge voxels (flat indices) decided the
+    other way."""
     u32 = np.ascontiguousarray(u, dtype=np.float32)
     deformed = _warp(moving, u32.astype(np.float64))
     out = {"whole": rms_cc(deformed, target)}
@@ -148,10 +178,14 @@ def evaluate(target, moving, target_masks, moving_masks, u, spacing=DEFAULT_SPAC
         out["uroi"] = rms_cc(deformed, target, region)
     out["structures"] = []
     for i in range(k):
-        d = _warp_mask_f32(moving_masks[i], u32).astype(bool)
-        t = target_masks[i].astype(bool)
-        rec = dsc(d, t)
-        contour = boundary(opening(d, radius))
-        rec["ssd"] = distance_stats(surface_distances(contour, boundary(t), spacing))
+        d, knife = deformed_mask(moving_masks[i], u32)
+        if flips is not None and len(flips[i]):
+            f = np.asarray(flips[i], dtype=np.int64)
+            if not np.isin(f, knife).all():
+                raise ValueError("only knife-edge voxels may be decided the other way")
+            d = d.copy()
+            d.flat[f] = ~d.flat[f]
+        rec = structure(d, target_masks[i], spacing, radius)
+        rec["knife_edge"] = [int(x) for x in knife]
         out["structures"].append(rec)
     return out

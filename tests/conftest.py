@@ -18,3 +18,18 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def progress(pytestconfig):
+    """print() that reaches the terminal while output capture is on: long tests (the oracle
+    at the benchmark sizes runs for minutes) report each step as it ends."""
+    capman = pytestconfig.pluginmanager.getplugin("capturemanager")
+
+    def say(msg):
+        if capman is None:
+            print(msg, flush=True)
+            return
+        with capman.global_and_fixture_disabled():
+            print(msg, flush=True)
+    return say

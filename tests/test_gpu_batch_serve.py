@@ -1,4 +1,5 @@
-"""Batched and served registration: every pair's result equals its result alone."""
+"""Batched and served registration: every pair's result equals its result alone, and a mixed
+batch of uneven pairs, batched and served, agrees with the FP64 oracle's Algorithm A."""
 import time
 
 import numpy as np
@@ -18,12 +19,12 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def _pairs():
+def _pairs(scale=1):
     return [
-        P.head_neck_pair(dims=(96, 64, 40), amp=4.0, k=3, levels=2, iters=6, seed=11),
-        P.pelvis_pair(dims=(128, 80, 24), amp=3.0, k=8, levels=3, iters=4, bulge=0.0, seed=12),
-        P.plain_pair(dims=(64, 64, 32), amp=3.0, iters=9, seed=13),
-        P.head_neck_pair(dims=(72, 100, 36), amp=4.0, k=1, levels=2, iters=(7), seed=14),
+        P.head_neck_pair(dims=(96, 64, 40), amp=4.0, k=3, levels=2, iters=6 * scale, seed=11),
+        P.pelvis_pair(dims=(128, 80, 24), amp=3.0, k=8, levels=3, iters=4 * scale, bulge=0.0, seed=12),
+        P.plain_pair(dims=(64, 64, 32), amp=3.0, iters=9 * scale, seed=13),
+        P.head_neck_pair(dims=(72, 100, 36), amp=4.0, k=1, levels=2, iters=7 * scale, seed=14),
     ]
 
 
@@ -65,7 +66,7 @@ def test_batch_rejects_when_pool_too_small():
 def test_served_equals_alone_and_reports_latency():
     import torch
     from paper_1301_0970_amd import cgdir
-    pairs = _pairs() * 2
+    pairs = _pairs(scale=10) * 2
     items = _items(pairs)
     prms = [cgdir.params_for_pair(p) for p in pairs]
     with cgdir.Context(4 << 30, max_slots=3) as ctx:
@@ -73,17 +74,18 @@ def test_served_equals_alone_and_reports_latency():
         alone = [ctx.register(*it, prm=pr).cpu().numpy() for it, pr in zip(items, prms)]
         outs = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
         say("serve submit")
-        tickets = []
-        for it, pr, o in zip(items, prms, outs):
-            tickets.append(ctx.submit(*it, pr, o))
-            time.sleep(0.002)
+        tickets = [ctx.submit(*it, pr, o) for it, pr, o in zip(items, prms, outs)]
         for t in tickets:
             assert ctx.wait(t, int(60e9)) == cgdir.OK
+        sts = []
         for t, a, o in zip(tickets, alone, outs):
             st = ctx.poll(t)
             assert st.state == cgdir.DONE
             assert st.t_submit_ns <= st.t_admit_ns <= st.t_done_ns
             np.testing.assert_array_equal(a, o.cpu().numpy())
+            sts.append(st)
+        # the requests shared the device: one was admitted before an earlier one finished
+        assert any(b.t_admit_ns < a.t_done_ns for i, a in enumerate(sts) for b in sts[i + 1:])
         with pytest.raises(cgdir.CgdirError):
             ctx.poll(987654)
 
@@ -354,3 +356,69 @@ def test_tuning_export_and_import():
             with pytest.raises(cgdir.CgdirError) as e:
                 c3.tuning_import(bad)
             assert e.value.code == cgdir.E_INVAL, bad
+
+
+def _mixed():
+    """Uneven pairs: structure counts 0 to 8, sigma 1 and 1.5, one in physical units
+    (1.97 x 1.97 x 2.5 mm voxels, sigmas in mm), one with contour terms at every level; each
+    with the oracle's parameters beside the library's."""
+    from paper_1301_0970_amd import cgdir
+    import oracle
+    out = []
+    a = P.plain_pair(dims=(64, 48, 30), amp=3.0, iters=30, seed=51)
+    out.append((a, {}))
+    b = P.head_neck_pair(dims=(72, 60, 36), amp=4.0, k=3, levels=2, iters=20, sigma=1.5, seed=52)
+    out.append((b, {}))
+    c = P.pelvis_pair(dims=(96, 80, 24), amp=3.0, k=8, levels=3, iters=15, bulge=0.0, seed=53)
+    out.append((c, {}))
+    d = P.head_neck_pair(dims=(60, 56, 40), amp=3.0, k=1, levels=2, iters=20, sigma=1.0, seed=54)
+    d.target_masks, d.moving_masks, d.signs = d.target_masks[:0], d.moving_masks[:0], ()
+    out.append((d, {}))
+    e = P.plain_pair(dims=(56, 52, 28), amp=3.0, iters=20, levels=2, seed=55)
+    out.append((e, dict(spacing=(1.97, 1.97, 2.5), sigma_fluid=2.0, sigma_diff=2.0)))
+    f = P.pelvis_pair(dims=(80, 64, 32), amp=3.0, k=2, levels=2, iters=20, bulge=0.0, seed=56)
+    out.append((f, dict(contour_level_mask=3)))
+    res = []
+    for pair, over in out:
+        res.append((pair, cgdir.params_for_pair(pair, **over), oracle.params_for(pair, **over)))
+    return res
+
+
+@pytest.mark.timeout(300)
+def test_mixed_batch_and_served_against_oracle(orc, progress):
+    """Each pair of an uneven mix, registered in one batch and served with overlapping requests,
+    against the oracle's Algorithm A: final field within 1e-2 voxel (max-abs), warped moving
+    image within 2.5 HU RMS."""
+    import torch
+    from paper_1301_0970_amd import cgdir
+    mix = _mixed()
+    pairs = [m[0] for m in mix]
+    items = _items(pairs)
+    prms = [m[1] for m in mix]
+    refs = []
+    for pair, _, op in mix:
+        progress("oracle: %s %s k %d" % (pair.name, pair.dims, pair.k))
+        u, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks, op)
+        refs.append((u, orc.warp(pair.moving, u)))
+    with cgdir.Context(2 << 30, max_slots=4) as ctx:
+        outs_b = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
+        progress("mixed batch")
+        rc, st = ctx.register_batch(items, prms, outs_b)
+        assert rc == cgdir.OK and st == [0] * len(pairs)
+        outs_s = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
+        progress("mixed served")
+        tickets = [ctx.submit(*it, pr, o) for it, pr, o in zip(items, prms, outs_s)]
+        for t in tickets:
+            assert ctx.wait(t, int(60e9)) == cgdir.OK
+        sts = [ctx.poll(t) for t in tickets]
+        assert any(b.t_admit_ns < a.t_done_ns for i, a in enumerate(sts) for b in sts[i + 1:])
+        for mode, outs in (("batched", outs_b), ("served", outs_s)):
+            for j, ((pair, _, _), (uo, wo), o) in enumerate(zip(mix, refs, outs)):
+                warped = ctx.warp(items[j][1], o).cpu().numpy().astype(np.float64)
+                ug = o.cpu().numpy()
+                err = float(np.abs(ug - uo).max())
+                rms = float(np.sqrt(np.mean((warped - wo) ** 2)))
+                progress("  %s %s %s k %d: max err %.3g voxel, warped RMS %.3g HU"
+                         % (mode, pair.name, pair.dims, pair.k, err, rms))
+                assert err <= 1e-2, (mode, pair.name)
+                assert rms <= 2.5, (mode, pair.name)

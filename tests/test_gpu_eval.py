@@ -1,10 +1,13 @@
 """cgdir_evaluate (section 2.3 metrics on the GPU) against the evaluation oracle.
 
-Integer results (voxel counts, contour and surface points) and the DSC built from them are
-compared exactly: the inside decision of the mask warp is taken in FP32 on both sides.  The
-surface distances are the same FP64 expression on both sides, so their statistics agree to
-rounding of the sums (1e-12).  RMS-ID and CC use the FP32 warp on the GPU and the FP64 warp in
-the oracle: relative 1e-5."""
+The oracle propagates each structure with the FP64 mask warp.  Whether a voxel is inside is an
+integer that floating point decides, so a voxel whose FP64 trilinear value lies within the
+oracle's knife-edge bound of 0.5 may be decided either way by the library's FP32 warp: those
+voxels are counted and reported, and the GPU's counts, DSC and contour statistics must equal
+the oracle's for one of the valid decisions of its knife-edge voxels (every combination is
+tried).  Surface distances are the same FP64 expression on both sides, so their statistics
+agree to rounding of the sums (1e-12).  RMS-ID and CC use the FP32 warp on the GPU and the
+FP64 warp in the oracle: relative 1e-5."""
 import sys
 
 import numpy as np
@@ -33,7 +36,27 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def compare(got, ref):
+MAX_KNIFE = 8   # knife-edge voxels per structure whose decisions are enumerated
+
+
+def same_structure(g, r):
+    if (g["deformed"], g["target"], g["overlap"]) != (r["deformed"], r["target"], r["overlap"]):
+        return False
+    if g["dsc"] != r["dsc"] or g["ssd"]["points"] != r["ssd"]["points"]:
+        return False
+    for key in ("mean", "sd", "p95"):
+        if np.isnan(r["ssd"][key]):
+            if not np.isnan(g["ssd"][key]):
+                return False
+        elif g["ssd"][key] != pytest.approx(r["ssd"][key], rel=1e-12, abs=1e-12):
+            return False
+    return True
+
+
+def compare(got, ref, inputs=None, say=say):
+    """inputs: (target_masks, moving_masks, u, spacing, radius) to enumerate the decisions of
+    knife-edge voxels when a structure differs from the oracle's FP64 decisions."""
+    from oracle import evaluate as ev
     for reg in ("whole", "uroi"):
         if reg not in ref:
             continue
@@ -42,18 +65,26 @@ def compare(got, ref):
         assert got[reg]["cc"] == pytest.approx(ref[reg]["cc"], rel=1e-5), reg
     assert len(got["structures"]) == len(ref["structures"])
     for i, (g, r) in enumerate(zip(got["structures"], ref["structures"])):
-        assert (g["deformed"], g["target"], g["overlap"]) == (r["deformed"], r["target"], r["overlap"]), i
-        assert g["dsc"] == r["dsc"], i
-        assert g["ssd"]["points"] == r["ssd"]["points"], i
-        for key in ("mean", "sd", "p95"):
-            if np.isnan(r["ssd"][key]):
-                assert np.isnan(g["ssd"][key]), (i, key)
-            else:
-                assert g["ssd"][key] == pytest.approx(r["ssd"][key], rel=1e-12, abs=1e-12), (i, key)
+        knife = r["knife_edge"]
+        say("  structure %d: %d knife-edge voxels" % (i, len(knife)))
+        if same_structure(g, r):
+            continue
+        assert inputs is not None and 0 < len(knife) <= MAX_KNIFE, (i, len(knife))
+        tmask, mmask, u, spacing, radius = inputs
+        base, _ = ev.deformed_mask(mmask[i], u)
+        ok = False
+        for bits in range(1, 1 << len(knife)):
+            d = base.copy()
+            f = [knife[j] for j in range(len(knife)) if (bits >> j) & 1]
+            d.flat[f] = ~d.flat[f]
+            if same_structure(g, ev.structure(d, tmask[i], spacing, radius)):
+                ok = True
+                break
+        assert ok, i
 
 
 @pytest.mark.parametrize("case", ["registered", "random_field", "anisotropic_r2"])
-def test_evaluate_matches_oracle(ctx, case):
+def test_evaluate_matches_oracle(ctx, case, progress):
     from oracle import evaluate as ev
     from paper_1301_0970_amd import cgdir
     pair = P.head_neck_pair(dims=(72, 60, 36), amp=4.0, k=3, levels=1, iters=20, sigma=1.0, seed=41)
@@ -73,7 +104,8 @@ def test_evaluate_matches_oracle(ctx, case):
                       spacing=kw.get("spacing", ev.DEFAULT_SPACING), radius=kw.get("opening_radius", 1),
                       margin=kw.get("uroi_margin", (5, 5, 4)))
     assert all(s["ssd"]["points"] > 0 for s in ref["structures"])
-    compare(got, ref)
+    compare(got, ref, (pair.target_masks, pair.moving_masks, u, kw.get("spacing", ev.DEFAULT_SPACING),
+                       kw.get("opening_radius", 1)), say=progress)
 
 
 def test_evaluate_identity_and_host_inputs(ctx):

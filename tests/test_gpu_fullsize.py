@@ -1,12 +1,8 @@
 """The pelvis-like workload at its full size (512 x 512 x 128, 8 structures), in the launch
 configuration the benchmark uses.
 
-* One teacher-forced iteration on the whole volume against the FP64 oracle on sampled
-  blocks: the oracle runs the same iteration on an 81^3 crop around each sample centre, and
-  the voxels within 6 of the centre are compared.  Their result depends on data within about
-  25 voxels (Gaussian radii 3 + 3, gradient 1, compose gather 2, warp gather |u| <= 8), so a
-  crop edge 34 voxels away is never seen, and where the crop meets the volume's border the
-  oracle clamps exactly as the volume does.
+* One teacher-forced iteration from a random smooth field (amplitude 6 voxels) against the
+  FP64 oracle's iteration from the same field, compared at every voxel.
 * The same iteration under every tile shape the autotuner tries: bitwise identical fields.
 * The full benchmark registration (3 levels x 150 iterations): properties that hold at any
   size (finite field, lower intensity error, higher overlap for every structure, positive
@@ -20,7 +16,6 @@ from paper_1301_0970_amd import phantom as P
 pytestmark = pytest.mark.gpu
 
 STEP_TOL = 1e-4
-CROP, INNER = 40, 6
 
 
 def say(msg):
@@ -37,7 +32,8 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def test_fullsize_step_on_sampled_blocks_and_all_tile_shapes(pelvis, orc):
+@pytest.mark.timeout(300)
+def test_fullsize_step_whole_volume_and_all_tile_shapes(pelvis, orc, progress):
     from paper_1301_0970_amd import cgdir
     pair = pelvis
     u0 = P.random_smooth_field(pair.dims, 6.0, 202)
@@ -46,29 +42,20 @@ def test_fullsize_step_on_sampled_blocks_and_all_tile_shapes(pelvis, orc):
                             signs=sg)
     t, m, tm, mm, ud = dev(pair.target), dev(pair.moving), dev(pair.target_masks), dev(pair.moving_masks), dev(u0)
     with cgdir.Context(4 << 30) as ctx:
-        say("full-size step: every tile shape")
+        progress("full-size step: every tile shape")
         first = ctx.register(t, m, tm, mm, prm, initial=ud).cpu().numpy()
         for i in range(18):           # the autotuner's candidate shapes, then the tuned one
             again = ctx.register(t, m, tm, mm, prm, initial=ud).cpu().numpy()
             assert np.array_equal(first, again), i
-    nx, ny, nz = pair.dims
-    centres = [(nx // 2, ny // 2, nz // 2), (3, 5, 2), (nx - 2, ny - 4, nz - 1), (140, 300, 64),
-               (400, 120, 100)]
-    for c in centres:
-        lo = [max(0, c[a] - CROP) for a in range(3)]
-        hi = [min(n, c[a] + CROP + 1) for a, n in enumerate(pair.dims)]
-        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
-        say("oracle block at %s" % (c,))
-        Ip = [orc.modified_image(pair.moving[sl], pair.moving_masks[i][sl], sg[i]) for i in range(pair.k)]
-        Tp = [orc.modified_image(pair.target[sl], pair.target_masks[i][sl], sg[i]) for i in range(pair.k)]
-        uo, _ = orc.step(pair.moving[sl], pair.target[sl], Ip, Tp, lam, pair.sigma, pair.sigma,
-                         u0[(slice(None),) + sl].astype(np.float64))
-        inner = tuple(slice(max(0, c[a] - INNER) - lo[a], min(n, c[a] + INNER + 1) - lo[a])
-                      for a, n in reversed(list(enumerate(pair.dims))))
-        gsl = tuple(slice(s.start + lo[a], s.stop + lo[a]) for s, a in zip(inner, (2, 1, 0)))
-        err = np.abs(first[(slice(None),) + gsl] - uo[(slice(None),) + inner]).max()
-        say("  max err %.3g" % err)
-        assert err <= STEP_TOL, c
+    progress("full-size step: the oracle's iteration on the whole volume")
+    Ip = [orc.modified_image(pair.moving, pair.moving_masks[i], sg[i]) for i in range(pair.k)]
+    Tp = [orc.modified_image(pair.target, pair.target_masks[i], sg[i]) for i in range(pair.k)]
+    uo, _ = orc.step(pair.moving, pair.target, Ip, Tp, lam, pair.sigma, pair.sigma, u0.astype(np.float64))
+    err = np.abs(first - uo)
+    idx = np.unravel_index(int(np.argmax(err)), err.shape)
+    progress("  max |du| %.3g, max err %.3g at (c, z, y, x) = %s"
+             % (float(np.abs(uo - u0).max()), float(err[idx]), tuple(int(i) for i in idx)))
+    assert err[idx] <= STEP_TOL
 
 
 def test_fullsize_registration_properties(pelvis):

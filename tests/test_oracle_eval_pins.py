@@ -95,23 +95,63 @@ def test_rms_and_cc():
     assert r["rms_id"] == pytest.approx(np.sqrt(np.mean((A - T)[region] ** 2)), rel=1e-12)
 
 
-def test_mask_warp_f32_matches_fp64_and_shifts():
+def test_deformed_mask_shifts_and_knife_edges():
+    """The mask warp moves a mask by whole voxels exactly (no knife-edge voxel); under a
+    half-voxel shift every voxel on the moving face has the value 0.5 exactly, counts as
+    inside, and is listed as knife-edge; elsewhere the decision is scipy's interpolation
+    thresholded at 0.5."""
+    from scipy import ndimage
     rng = np.random.default_rng(8)
     m = (rng.uniform(size=(11, 13, 17)) > 0.6).astype(np.uint8)
     u = np.zeros((3, 11, 13, 17), np.float32)
     u[0] = 1.0
     u[2] = -2.0
-    got = oracle.warp_mask_f32(m, u)
+    got, knife = ev.deformed_mask(m, u)
     # pull-back by whole voxels with a clamped border: out(x, y, z) = m(x + 1, y, z - 2)
     zi = np.clip(np.arange(11) - 2, 0, 10)
     xi = np.clip(np.arange(17) + 1, 0, 16)
-    np.testing.assert_array_equal(got, m[zi][:, :, xi])
+    np.testing.assert_array_equal(got, m[zi][:, :, xi].astype(bool))
+    assert len(knife) == 0
+    cube = np.zeros((8, 9, 10), np.uint8)
+    cube[2:6, 3:7, 3:8] = 1
+    half = np.zeros((3,) + cube.shape, np.float32)
+    half[0] = 0.5
+    got, knife = ev.deformed_mask(cube, half)
+    face = np.zeros(cube.shape, bool)
+    face[2:6, 3:7, 2] = True          # value (0 + 1) / 2 at x = 2
+    face[2:6, 3:7, 7] = True          # value (1 + 0) / 2 at x = 7
+    np.testing.assert_array_equal(np.sort(knife), np.flatnonzero(face))
+    expect = np.zeros(cube.shape, bool)
+    expect[2:6, 3:7, 2:8] = True
+    np.testing.assert_array_equal(got, expect)
     from paper_1301_0970_amd import phantom as P
     u = P.random_smooth_field((17, 13, 11), 3.0, 9).astype(np.float32)
-    f32 = oracle.warp_mask_f32(m, u)
-    val = oracle.warp(m.astype(np.float64), u.astype(np.float64))
-    decided = np.abs(val - 0.5) > 1e-5
-    np.testing.assert_array_equal(f32[decided], (val >= 0.5)[decided])
+    got, knife = ev.deformed_mask(m, u)
+    nz, ny, nx = m.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    coords = [np.clip(z + u[2].astype(np.float64), 0, nz - 1), np.clip(y + u[1].astype(np.float64), 0, ny - 1),
+              np.clip(x + u[0].astype(np.float64), 0, nx - 1)]
+    val = ndimage.map_coordinates(m.astype(np.float64), coords, order=1, mode="nearest")
+    decided = np.abs(val - 0.5) > 1e-9
+    np.testing.assert_array_equal(got[decided], (val >= 0.5)[decided])
+    np.testing.assert_array_equal(np.sort(knife), np.flatnonzero(np.abs(val - 0.5) <= ev.KNIFE_EDGE))
+
+
+def test_evaluate_flips_only_knife_edge_voxels():
+    """A knife-edge voxel decided the other way changes the overlap counts by one; any other
+    voxel is refused."""
+    T = np.zeros((8, 9, 10), np.uint8)
+    T[2:6, 3:7, 3:8] = 1
+    u = np.zeros((3,) + T.shape, np.float32)
+    u[0] = 0.5
+    img = T.astype(np.float32)
+    r0 = ev.evaluate(img, img, T[None], T[None], u, spacing=(1, 1, 1), radius=0)
+    knife = r0["structures"][0]["knife_edge"]
+    assert len(knife) == 32
+    r1 = ev.evaluate(img, img, T[None], T[None], u, spacing=(1, 1, 1), radius=0, flips=[knife[:1]])
+    assert r1["structures"][0]["deformed"] == r0["structures"][0]["deformed"] - 1
+    with pytest.raises(ValueError):
+        ev.evaluate(img, img, T[None], T[None], u, spacing=(1, 1, 1), radius=0, flips=[[0]])
 
 
 def test_evaluate_identity_and_known_shift():

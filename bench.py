@@ -2,18 +2,27 @@
 """Throughput benchmark of contour-guided demons registration on one MI355X.
 
 One step = one full registration (Algorithm A: pyramid set-up, coarse demons levels,
-finest-level CG-DIR loop) of the synthetic workload, through the C-ABI, with the inputs
+finest-level CG-DIR loop) of the pelvis workload, through the C-ABI, with the inputs
 already resident in HBM.  value = voxel-iterations per second, sum over levels of
 (voxels x iterations) / wall time per step.
 
 Also reported on the same JSON line:
-  roofline      the dominant kernel (finest-level step or smooth) -- algorithmic bytes per launch
-                (bytes per voxel x voxels) over its average launch duration, from HIP
-                events on the library's stream during a profiled pass of the same steps;
-                traffic = HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
-                summary in profiles/, when it was taken on the current kernel source.
-  cpu_baseline  the FP64 oracle on a bounded sample of the same workload (rank 0 only).
-  served        with --serve: open-loop Poisson arrivals, p50/p99 latency.
+  roofline      the finest-level iteration (the step launch plus the smoothing launch):
+                algorithmic bytes of one iteration (u read and written, I0, T0, the mask
+                bit-planes: 34 B per voxel with contour terms) over the summed average
+                launch durations, from HIP events on the library's stream during a
+                profiled pass of the same steps, against 8 TB/s; per-kernel shares of those
+                bytes; the HBM bytes the counters measured (rocprofv3 FETCH_SIZE /
+                WRITE_SIZE) and the VALU instructions (SQ_INSTS_VALU) per launch, read from
+                the summaries in profiles/ when they were taken on the current kernel
+                source; the VALU-issue ceiling those instructions imply; `bound` is the
+                resource closer to its ceiling.
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload, on all the host
+                threads it is given and on one thread (rank 0 only).
+  batched       the uneven batch of 32 pairs in one call against the same pairs one at a time.
+  served        Poisson arrivals at 4 requests/s for 120 s (pairs drawn like the batch),
+                continuous batching against a serial FIFO on the same schedule, and both again
+                at a rate between the two modes' capacities.
 """
 import argparse
 import hashlib
@@ -21,6 +30,7 @@ import json
 import math
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -30,20 +40,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue of MI355X without packed FP32: 256 compute units, each issuing one wave64 vector
+# instruction per clock (four SIMDs of 16 lanes, four clocks per wave64 instruction), 2.4 GHz
+VALU_WAVE_INSTS_PER_S = 256 * 2.4e9
+VALU_LANE_OPS_PEAK = VALU_WAVE_INSTS_PER_S * 64
 
-# algorithmic bytes per voxel of each finest-level kernel (fields FP32 SoA, mask bit-planes
-# one byte per voxel per side).  step (force, fluid smoothing, compose) reads the warped
-# image I0~ (4), T0 (4), u (12) and, with contour terms, the stencil structure bits and the
-# target bits (1 + 1), and, with the stopping metric, the UROI (1); it writes u_c (12).
-# smooth (diffusion smoothing, then the warp of I0) reads u_c (12) and I0 (4, gathered about
-# once) and writes u (12), I0~ (4) and, with contour terms, the structure bits (1).  The
-# K_i~ values and moving-mask bits near structures are data dependent and left out.
-def bytes_per_voxel(kernel, k, metric):
+
+# Algorithmic bytes per voxel of one finest-level iteration (fields FP32 SoA, one mask
+# bit-plane byte per voxel per side): u read and written (12 + 12), I0 (4, gathered about
+# once: u is smooth), T0 (4), the moving and target bit-planes (1 + 1) with contour terms,
+# the UROI (1) with the stopping metric.  Everything else the design moves (the composite
+# update u_c, the warped image and its structure bits, K~) is a design intermediate.
+def iteration_bytes_per_voxel(k, metric):
+    return 32 + (2 if k else 0) + (1 if metric else 0)
+
+
+# The same bytes split by kernel: the step kernel reads u, T0 and the bit-planes; the
+# smoothing kernel gathers I0 and writes u.
+def kernel_bytes_per_voxel(kernel, k, metric):
     if kernel == "step":
-        return 4 + 4 + 12 + 12 + (2 if k else 0) + (1 if metric else 0)
-    if kernel == "smooth":
-        return 12 + 4 + 12 + 4 + (1 if k else 0)
-    return None
+        return 12 + 4 + (2 if k else 0) + (1 if metric else 0)
+    return 4 + 12
 
 
 KERNEL_SYMBOL = {"step": "k_step_batch", "smooth": "k_smooth_batch"}
@@ -78,6 +95,44 @@ def slab_of(pair, planes, halo):
     return pair
 
 
+def _pair_from_spec(spec):
+    from paper_1301_0970_amd import phantom as P
+    return P.from_spec(spec)
+
+
+def generate(specs, workers):
+    """The pairs of a list of specs, drawn in parallel worker processes (numpy only; started
+    before this process touches the GPU)."""
+    if workers <= 1 or len(specs) <= 1:
+        return [_pair_from_spec(s) for s in specs]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(workers, len(specs))) as pool:
+        return pool.map(_pair_from_spec, specs, chunksize=1)
+
+
+def host_threads():
+    """Threads the oracle's OpenMP runtime uses (OMP_NUM_THREADS, else the CPUs this process
+    may run on)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.split(",")[0].isdigit():
+        return int(env.split(",")[0])
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except Exception:
+        return None
+    info = {}
+    for line in out.splitlines():
+        if ":" in line:
+            key, v = line.split(":", 1)
+            info[key.strip()] = v.strip()
+    return {"model": info.get("Model name"), "cpus": info.get("CPU(s)"),
+            "sockets": info.get("Socket(s)"), "threads_per_core": info.get("Thread(s) per core")}
+
+
 def copy_peak_gbs(torch, mib=1024, reps=10):
     """Device-to-device copy bandwidth (read + write bytes per second) with HIP events."""
     n = mib << 18
@@ -104,94 +159,111 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(workload, kernel):
-    """HBM bytes per launch from profiles/<kernel>_<workload>_pmc.md, if it was measured on
-    the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.md" % (kernel, workload))
+def read_profile(workload, what):
+    """Key/value lines `<name>: <number>` of profiles/iteration_<workload>_<what>.md when the
+    summary was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "iteration_%s_%s.md" % (workload, what))
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+    if not m_hash or m_hash.group(1) != kernel_source_hash():
         return None
-    return float(m_bytes.group(1))
+    return {m.group(1): float(m.group(2))
+            for m in re.finditer(r"^([a-z_]+):\s*([-0-9.eE+]+)\s*$", txt, re.M)}
 
 
-def cpu_baseline(pair, target_vi=3.0e8):
+def roofline(stats, pair, metric, workload, copy_gbs):
+    """The finest-level iteration against HBM bandwidth and VALU issue."""
+    fin = {s["name"].split("@")[0]: s for s in stats if s["name"].endswith("@L0")}
+    st, sm = fin["step"], fin["smooth"]
+    n = st["voxels"] / st["launches"]
+    t_step = st["total_ms"] / st["launches"]
+    t_smooth = sm["total_ms"] / sm["launches"]
+    t_iter = t_step + t_smooth
+    bpv = iteration_bytes_per_voxel(pair.k, metric)
+    alg = bpv * n
+    achieved = alg / (t_iter * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+           "kernel": "finest-level iteration: k_step_batch + k_smooth_batch (%d voxels)" % n,
+           "bytes_per_voxel": bpv, "algorithmic_bytes_per_iteration": alg,
+           "iteration_ms": round(t_iter, 5), "copy_measured_gbs": round(copy_gbs, 1)}
+    per = {}
+    for name, s, t in (("step", st, t_step), ("smooth", sm, t_smooth)):
+        b = kernel_bytes_per_voxel(name, pair.k, metric) * n
+        per[name] = {"avg_launch_ms": round(t, 5), "algorithmic_bytes": b,
+                     "frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    hbm = read_profile(workload, "hbm")
+    if hbm:
+        traffic = hbm["step_hbm_bytes_per_launch"] + hbm["smooth_hbm_bytes_per_launch"]
+        out["traffic"] = traffic
+        out["traffic_over_algorithmic"] = round(traffic / alg, 3)
+        out["measured_gbs"] = round(traffic / (t_iter * 1e-3) / 1e9, 1)
+        for name in per:
+            per[name]["hbm_bytes"] = hbm[name + "_hbm_bytes_per_launch"]
+    sq = read_profile(workload, "valu")
+    busy_hbm = (out["measured_gbs"] / copy_gbs) if hbm else None
+    if sq:
+        insts = sq["step_valu_insts_per_launch"] + sq["smooth_valu_insts_per_launch"]
+        ceiling_ms = insts / VALU_WAVE_INSTS_PER_S * 1e3
+        out["valu"] = {"wave_insts_per_iteration": insts,
+                       "insts_per_voxel": round(64 * insts / n, 1),
+                       "ceiling_ms": round(ceiling_ms, 5),
+                       "achieved_lane_ops": round(64 * insts / (t_iter * 1e-3) / 1e12, 2),
+                       "peak_lane_ops": round(VALU_LANE_OPS_PEAK / 1e12, 2),
+                       "unit": "T lane-instructions/s",
+                       "frac": round(ceiling_ms / t_iter, 4)}
+        for name in per:
+            v = sq[name + "_valu_insts_per_launch"]
+            per[name]["valu_insts_per_voxel"] = round(64 * v / n, 1)
+        if busy_hbm is None or out["valu"]["frac"] > busy_hbm:
+            out["bound"] = "alu"
+    out["bound_evidence"] = ("VALU issue %s of its ceiling, HBM traffic %s of the copy-measured rate"
+                             % ("%.2f" % out["valu"]["frac"] if sq else "unmeasured",
+                                "%.2f" % busy_hbm if busy_hbm is not None else "unmeasured"))
+    out["kernels"] = per
+    return out
+
+
+def cpu_baseline(pair, target_vi=3.0e8, one_thread_vi=4.0e7):
     """The oracle's Algorithm A on the full-size inputs of the workload, with the same number
-    of iterations at every level, as many as make about `target_vi` voxel-iterations (8 for
-    the pelvis workload: 10-15 s of work on 16 cores), at most the workload's own count."""
+    of iterations at every level: as many as make about `target_vi` voxel-iterations on all
+    the host threads it is given (8 for the pelvis workload), and one iteration per level on
+    one thread."""
+    import ctypes
     import oracle
     per_iter, dims = 0, pair.dims
     for _ in range(pair.levels):
         per_iter += dims[0] * dims[1] * dims[2]
         dims = tuple((n + 1) // 2 for n in dims)
+
+    def run(it):
+        prm = oracle.params_for(pair, iters=(it,) * pair.levels)
+        t0 = time.time()
+        oracle.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks, prm)
+        return per_iter * it / (time.time() - t0), time.time() - t0
+
     it = max(1, min(max(pair.iters), int(math.ceil(target_vi / per_iter))))
-    prm = oracle.params_for(pair, iters=(it,) * pair.levels)
-    t0 = time.time()
-    oracle.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks, prm)
-    dt = time.time() - t0
-    vi = 0
-    dims = pair.dims
-    for _ in range(pair.levels):
-        vi += dims[0] * dims[1] * dims[2] * it
-        dims = tuple((n + 1) // 2 for n in dims)
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
-    return {"value": vi / dt, "unit": "voxel-iter/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 oracle, Algorithm A on the full %dx%dx%d inputs with %d iterations per "
-                      "level (%d levels, %.0f M voxel-iterations, %.1f s)"
-                      % (pair.dims + (it, pair.levels, vi / 1e6, dt))}
-
-
-def served(cgdir, P, torch, duration, rate, pool_bytes, distinct):
-    """Open-loop Poisson arrivals; each request registers a pair drawn like the batched
-    workload (a pool of `distinct` pre-generated pairs is cycled).  The same arrival schedule
-    is replayed twice: with continuous batching (8 slots) and as a serial FIFO (1 slot)."""
-    times, specs = P.serve_schedule(rate=rate, duration=duration)
-    pool_specs = specs[:distinct]
-    pairs = [P.from_spec(s) for s in pool_specs]
-    dev = torch.device("cuda")
-    items = [(torch.from_numpy(p.target).to(dev), torch.from_numpy(p.moving).to(dev),
-              torch.from_numpy(p.target_masks).to(dev), torch.from_numpy(p.moving_masks).to(dev))
-             for p in pairs]
-    outs = [torch.empty((3,) + p.target.shape, device=dev) for p in pairs]
-    prms = [cgdir.params_for_pair(p) for p in pairs]
-
-    def replay(slots):
-        lat = []
-        with cgdir.Context(pool_bytes, max_slots=slots) as ctx:
-            for it, pr, o in zip(items, prms, outs):   # warm-up: tile shapes tuned
-                ctx.register(*it, pr, o)
-            start = time.time()
-            tickets = []
-            for i, t in enumerate(times):
-                now = time.time() - start
-                if t > now:
-                    time.sleep(t - now)
-                j = i % len(items)
-                # requests for the same pair share its output tensor: they carry the same
-                # inputs, so whatever overlaps writes the same values
-                tickets.append(ctx.submit(*items[j], prms[j], outs[j]))
-            for t in tickets:
-                rc = ctx.wait(t)
-                if rc != cgdir.OK:
-                    raise RuntimeError("served request failed: %s" % cgdir.strerror(rc))
-            end = time.time()
-            for t in tickets:
-                st = ctx.poll(t)
-                lat.append((st.t_done_ns - st.t_submit_ns) / 1e6)
-        lat = np.array(lat)
-        return {"slots": slots, "p50_ms": float(np.percentile(lat, 50)),
-                "p99_ms": float(np.percentile(lat, 99)),
-                "registrations_per_s": len(lat) / (end - start)}
-
-    log("served: continuous batching")
-    cont = replay(8)
-    log("served: serial FIFO")
-    fifo = replay(1)
-    return {"requests": len(times), "rate_per_s": rate, "duration_s": duration,
-            "distinct_pairs": len(items), "continuous_batching": cont, "serial_fifo": fifo}
+    cores = host_threads()
+    value, dt = run(it)
+    res = {"value": value, "unit": "voxel-iter/s", "cores": cores, "kind": "oracle",
+           "sample": "FP64 oracle, Algorithm A on the full %dx%dx%d inputs with %d iterations per "
+                     "level (%d levels, %.0f M voxel-iterations, %.1f s on %d threads)"
+                     % (pair.dims + (it, pair.levels, per_iter * it / 1e6, dt, cores)),
+           "host": cpu_model()}
+    # one thread: the OpenMP runtime the oracle links, asked for one thread for this call
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(1)
+    try:
+        it1 = max(1, int(round(one_thread_vi / per_iter)))
+        v1, dt1 = run(it1)
+    finally:
+        gomp.omp_set_num_threads(cores)
+    res["one_thread"] = {"value": v1, "unit": "voxel-iter/s", "cores": 1,
+                         "sample": "%d iteration(s) per level, %.0f M voxel-iterations, %.1f s"
+                                   % (it1, per_iter * it1 / 1e6, dt1)}
+    return res
 
 
 def evaluated(cgdir, torch, pair, pool):
@@ -303,12 +375,10 @@ def warm_start(cgdir, torch, pair, pool, iters=30):
     return out
 
 
-def batched(cgdir, P, torch, n_pairs):
+def batched(cgdir, torch, pairs):
     """The uneven batch (sizes and structure counts drawn per pair): all pairs in one
     cgdir_register_batch call vs the same pairs registered one at a time, both timed after a
     pass of each that lets the autotuner settle every tile-shape group they use."""
-    specs = P.batch_specs(n_pairs)
-    pairs = [P.from_spec(s) for s in specs]
     dev = torch.device("cuda")
     items = [(torch.from_numpy(p.target).to(dev), torch.from_numpy(p.moving).to(dev),
               torch.from_numpy(p.target_masks).to(dev), torch.from_numpy(p.moving_masks).to(dev))
@@ -334,11 +404,87 @@ def batched(cgdir, P, torch, n_pairs):
         batch = time.perf_counter() - t0
         if rc != cgdir.OK:
             raise RuntimeError("batch failed: %s" % cgdir.strerror(rc))
-    return {"pairs": n_pairs, "voxel_iterations": vi,
+    return {"pairs": len(pairs), "voxel_iterations": vi,
             "batched_value": vi / batch, "batched_ms": batch * 1e3,
             "one_at_a_time_value": vi / serial, "one_at_a_time_ms": serial * 1e3,
             "speedup": serial / batch, "unit": "voxel-iter/s",
             "sizes": [list(p.dims) for p in pairs], "structures": [p.k for p in pairs]}
+
+
+def served(cgdir, torch, pairs, times, slots, pool_bytes):
+    """Open-loop arrivals at `times` (seconds); request i registers pairs[i % len(pairs)] (inputs
+    and outputs device-resident).  Latency = completion - submission (steady clock)."""
+    dev = torch.device("cuda")
+    items = [(torch.from_numpy(p.target).to(dev), torch.from_numpy(p.moving).to(dev),
+              torch.from_numpy(p.target_masks).to(dev), torch.from_numpy(p.moving_masks).to(dev))
+             for p in pairs]
+    outs = [torch.empty((3,) + p.target.shape, device=dev) for p in pairs]
+    prms = [cgdir.params_for_pair(p) for p in pairs]
+    lat = []
+    with cgdir.Context(pool_bytes, max_slots=slots) as ctx:
+        for it, pr, o in zip(items, prms, outs):   # warm-up: tile shapes tuned
+            ctx.register(*it, pr, o)
+        torch.cuda.synchronize()
+        start = time.time()
+        tickets = []
+        for i, t in enumerate(times):
+            now = time.time() - start
+            if t > now:
+                time.sleep(t - now)
+            j = i % len(items)
+            # requests for the same pair share its output tensor: they carry the same inputs,
+            # so whatever overlaps writes the same values
+            tickets.append(ctx.submit(*items[j], prms[j], outs[j]))
+        for t in tickets:
+            rc = ctx.wait(t)
+            if rc != cgdir.OK:
+                raise RuntimeError("served request failed: %s" % cgdir.strerror(rc))
+        sts = [ctx.poll(t) for t in tickets]
+    lat = np.array([(s.t_done_ns - s.t_submit_ns) / 1e6 for s in sts])
+    wait = np.array([(s.t_admit_ns - s.t_submit_ns) / 1e6 for s in sts])
+    first = min(s.t_submit_ns for s in sts)
+    last = max(s.t_done_ns for s in sts)
+    # the most requests running at once (admitted, not yet done)
+    ev = sorted([(s.t_admit_ns, 1) for s in sts] + [(s.t_done_ns, -1) for s in sts])
+    run = peak = 0
+    for _, d in ev:
+        run += d
+        peak = max(peak, run)
+    return {"slots": slots, "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "mean_ms": round(float(lat.mean()), 2),
+            "queue_wait_p99_ms": round(float(np.percentile(wait, 99)), 2),
+            "registrations_per_s": round(len(sts) / ((last - first) / 1e9), 3),
+            "max_co_resident": peak}
+
+
+def serving(cgdir, P, torch, pairs, batch_res, rate, duration, high_seconds):
+    times, _ = P.serve_schedule(rate=rate, duration=duration)
+    pool = 24 << 30
+    log("served: %d requests at %.1f/s, continuous batching" % (len(times), rate))
+    cont = served(cgdir, torch, pairs, times, 8, pool)
+    log("served: serial FIFO")
+    fifo = served(cgdir, torch, pairs, times, 1, pool)
+    out = {"requests": len(times), "rate_per_s": rate, "duration_s": duration,
+           "distinct_pairs": len(pairs), "continuous_batching": cont, "serial_fifo": fifo}
+    if batch_res and high_seconds > 0:
+        # a rate between the capacities the batch measured: pairs per second one at a time
+        # (the serial FIFO's) and in one batched call
+        n = batch_res["pairs"]
+        cap_fifo = n / (batch_res["one_at_a_time_ms"] / 1e3)
+        cap_cb = n / (batch_res["batched_ms"] / 1e3)
+        hi = 0.5 * (cap_fifo + cap_cb) if cap_cb > cap_fifo * 1.02 else 1.1 * cap_fifo
+        t_hi, _ = P.serve_schedule(rate=hi, duration=high_seconds)
+        log("served: %d requests at %.1f/s, continuous batching" % (len(t_hi), hi))
+        c2 = served(cgdir, torch, pairs, t_hi, 8, pool)
+        log("served: serial FIFO")
+        f2 = served(cgdir, torch, pairs, t_hi, 1, pool)
+        out["between_capacities"] = {"rate_per_s": round(hi, 2), "duration_s": high_seconds,
+                                     "requests": len(t_hi),
+                                     "capacity_fifo_per_s": round(cap_fifo, 2),
+                                     "capacity_batched_per_s": round(cap_cb, 2),
+                                     "continuous_batching": c2, "serial_fifo": f2}
+    return out
 
 
 def main():
@@ -348,17 +494,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pelvis", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", action="store_true", help="also run the served workload")
-    ap.add_argument("--batch", type=int, default=0, metavar="PAIRS",
-                    help="also run the uneven batched workload with this many pairs (32 in full)")
-    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--batch", type=int, default=32, metavar="PAIRS",
+                    help="pairs of the uneven batched workload (0: skip it)")
+    ap.add_argument("--serve-seconds", type=float, default=120.0,
+                    help="duration of the served workload's arrivals (0: skip serving)")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-distinct", type=int, default=32,
+                    help="distinct pairs the served requests cycle through")
+    ap.add_argument("--serve-high-seconds", type=float, default=30.0,
+                    help="duration of the run between the two modes' capacities (0: skip it)")
     ap.add_argument("--warm-start", action="store_true",
                     help="also time a finest-level re-registration started from the full result")
     ap.add_argument("--cold-start", action="store_true",
                     help="also time the first registration of a fresh context, untuned and with imported tile shapes")
     ap.add_argument("--evaluate", action="store_true",
                     help="also evaluate (section 2.3 metrics) CG-DIR, CG-DIR with contour terms at every level and plain demons on the workload")
-    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -369,10 +519,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_1301_0970_amd import cgdir, phantom as P
+    from paper_1301_0970_amd import phantom as P
 
     if args.copy_probe:
+        import torch
         n = args.copy_probe << 18   # float32 elements
         src = torch.ones(n, device="cuda")
         dst = torch.empty_like(src)
@@ -382,9 +532,23 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}))
         return
 
+    # every input is drawn before this process touches the GPU (worker processes)
     desc, make = WORKLOADS[args.workload]
     log("generating %s" % args.workload)
     pair = make(P)
+    workers = min(16, len(os.sched_getaffinity(0)))
+    batch_pairs, serve_pairs = [], []
+    if args.batch:
+        log("generating the uneven batch (%d pairs)" % args.batch)
+        batch_pairs = generate(P.batch_specs(args.batch), workers)
+    if args.serve_seconds > 0:
+        _, specs = P.serve_schedule(rate=args.serve_rate, duration=args.serve_seconds)
+        log("generating %d distinct served pairs" % min(args.serve_distinct, len(specs)))
+        serve_pairs = generate(specs[:args.serve_distinct], workers)
+
+    import torch
+    from paper_1301_0970_amd import cgdir
+
     dev = torch.device("cuda", 0)
     t = torch.from_numpy(pair.target).to(dev)
     m = torch.from_numpy(pair.moving).to(dev)
@@ -415,24 +579,12 @@ def main():
             ctx.register(t, m, tm, mm, prm, out)
         torch.cuda.synchronize()
         stats = ctx.kernel_stats()
-    finest = {s["name"].split("@")[0]: s for s in stats if s["name"].endswith("@L0")}
-    dom = max((n for n in finest if n in KERNEL_SYMBOL), key=lambda n: finest[n]["total_ms"])
-    s = finest[dom]
-    bpv = bytes_per_voxel(dom, pair.k, prm.stop_mode != 0)
-    per_launch_bytes = bpv * s["voxels"] / s["launches"]
-    avg_ms = s["total_ms"] / s["launches"]
-    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(args.workload, dom)
     log("copy probe")
     copy_gbs = copy_peak_gbs(torch)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "copy_measured_gbs": round(copy_gbs, 1),
-                "kernel": "%s (%s), finest level" % (dom, KERNEL_SYMBOL[dom]),
-                "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": per_launch_bytes,
-                "bytes_per_voxel": bpv}
+    roof = roofline(stats, pair, prm.stop_mode != 0, args.workload, copy_gbs)
     per_kernel = {x["name"]: {"launches": x["launches"], "avg_ms": round(x["total_ms"] / x["launches"], 5)}
                   for x in stats}
+    del t, m, tm, mm, out
 
     result = {
         "metric": "voxel-iterations/s + HBM GB/s vs roofline; served p50/p99 latency per registration",
@@ -449,7 +601,7 @@ def main():
         "data": "synthetic (seeded phantom standing in for clinical CT)",
         "config": {"workload": desc, "dims": list(pair.dims), "structures": pair.k,
                    "levels": pair.levels, "iters": list(pair.iters), "voxel_iterations": vi},
-        "roofline": roofline,
+        "roofline": roof,
         "kernels": per_kernel,
     }
     if not args.no_cpu_baseline:
@@ -464,13 +616,13 @@ def main():
     if args.evaluate:
         log("evaluation")
         result["evaluation"] = evaluated(cgdir, torch, pair, pool + (1 << 30))
-    if args.batch:
+    if batch_pairs:
         log("batched workload")
-        result["batched"] = batched(cgdir, P, torch, args.batch)
-    if args.serve:
+        result["batched"] = batched(cgdir, torch, batch_pairs)
+    if serve_pairs:
         log("served workload")
-        result["served"] = served(cgdir, P, torch, args.serve_seconds, args.serve_rate,
-                                  32 << 30, 16)
+        result["served"] = serving(cgdir, P, torch, serve_pairs, result.get("batched"), args.serve_rate,
+                                   args.serve_seconds, args.serve_high_seconds)
     print(json.dumps(result), flush=True)
 
 

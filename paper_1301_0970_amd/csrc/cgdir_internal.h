@@ -53,7 +53,9 @@ struct StepArgs {
     Dims d;
     int k;                    // active structures (<= kMaxStructs)
     float lam[kMaxStructs];   // lambda_i
-    float lam_sum;            // lambda_0 + ... + lambda_{k-1}, summed in this order
+    float far_l1;             // 1 + lambda_0 + ... + lambda_{k-1}, summed in this order
+    float far_cx, far_cz;     // 2 far_l1 gx^2 and 2 far_l1 gz^2 (gx, gz = gs[0], gs[1])
+    float gs2[2];             // gs[0]^2 and gs[1]^2
     uint32_t neg;             // bit i: s_i = -1 (else +1); the modified images use s_i / 2
     float c0;                 // CT-number offset
     float inv_norm;           // 1 / norm_range

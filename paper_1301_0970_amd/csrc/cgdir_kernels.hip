@@ -254,24 +254,36 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
                                          const int ks[3], float du[3], float *dout)
 {
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
-    const float g0x = a.gs[0] * (w[2] - w[1]);
-    const float g0y = a.gs[0] * (w[4] - w[3]);
-    const float g0z = a.gs[1] * (w[6] - w[5]);
+    // central differences of I0~ (times 2 h: the gradient is gs times these)
+    const float ex = w[2] - w[1], ey = w[4] - w[3], ez = w[6] - w[5];
     const float d = t0 - w[0];
     *dout = d;
-    const float a02 = __builtin_fmaf(g0z, g0z, __builtin_fmaf(g0y, g0y, g0x * g0x));
+    const float a02 = __builtin_fmaf(a.gs2[1], ez * ez, a.gs2[0] * __builtin_fmaf(ey, ey, ex * ex));
     du[0] = du[1] = du[2] = 0.f;
     // n = grad I0~ / |grad I0~| undefined at 0: no step (also below the smallest normal
     // float, where the step is below 1e-19 voxel; NaN goes on and is reported)
     if (a02 < 1.17549435e-38f) return;
+    const uint32_t kb = f[0] | f[1] | f[2] | f[3] | f[4] | f[5] | f[6] | tb;
+    if (kb == 0) {
+        // no structure touches the stencil: every contour term of Eq.7 reduces to lambda_i a0 d
+        // (numerator) and lambda_i a0^2 (denominator), so v n = L a0 d n / (L a0^2 + d^2) with
+        // L = 1 + sum lambda_i, which is L d grad I0~ / (L a0^2 + d^2): the unit vector n is
+        // never formed.  In voxels along each axis the step is that times 2 gs, i.e. 2 gs^2 L d
+        // e / (L a0^2 + d^2) for the difference e (beta = d^2, Thirion).
+        const float q = d * __builtin_amdgcn_rcpf(__builtin_fmaf(a.far_l1, a02, d * d));  // ~1 ulp
+        du[0] = (a.far_cx * q) * ex;
+        du[1] = (a.far_cx * q) * ey;
+        du[2] = (a.far_cz * q) * ez;
+        return;
+    }
+    const float g0x = a.gs[0] * ex, g0y = a.gs[0] * ey, g0z = a.gs[1] * ez;
     const float inv = __builtin_amdgcn_rsqf(a02);  // hardware 1/sqrt, ~1 ulp
     const float a0 = a02 * inv;
     const float nxv = g0x * inv, nyv = g0y * inv, nzv = g0z * inv;
     float num = a0 * d;
     float den = __builtin_fmaf(d, d, a02);  // beta = d^2 (Thirion)
-    float lam_off = a.lam_sum;
-    const uint32_t kb = f[0] | f[1] | f[2] | f[3] | f[4] | f[5] | f[6] | tb;
-    if (kb) {
+    float lam_off;
+    {
         const int xm = max(gx - 1, 0), xp = min(gx + 1, nx - 1);
         const int ym = max(gy - 1, 0), yp = min(gy + 1, ny - 1);
         const int zm = max(gz - 1, 0), zp = min(gz + 1, nz - 1);
@@ -569,15 +581,28 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     constexpr bool kFr32 = kLdsBase + 16 * WCELLS <= kLdsMax;
     constexpr bool kStageK = kMasked && TY == 16 && kLdsBase + 16 * WCELLS + kKrBytes <= kLdsMax;
     using FrT = typename std::conditional<kFr32, uint32_t, uint8_t>::type;
-    __shared__ float Wr[4][WCELLS];    // I0~ planes, slot = plane & 3
-    __shared__ FrT Fr[kMasked ? 4 : 1][kMasked ? WCELLS : 1];  // their stencil structure bits
-    __shared__ float Kr[kStageK ? 3 : 1][kStageK ? WCELLS : 1];  // K~ where the bits are nonzero,
-                                                                 // slot = plane % 3
-    __shared__ float raw[3][HT][WD];   // du on the tile + R halo
-    __shared__ float xs[3][HT][kTileX];
-    __shared__ float Us[3][3][UCELLS];  // u planes z-1..z+1, slot (p - z0 + 1) % 3
-    __shared__ float dq[TY][kTileX];   // squared metric terms of the tile's voxels
-    __shared__ float lamt[2][kMaxStructs];  // lambda_i; the sum of the other weights
+    // One LDS buffer laid out by hand, in order of access density: the arrays read at many
+    // constant offsets from one address come first, below 64 KiB, where those offsets fit the
+    // LDS instructions' own offset field instead of costing an address add each.
+    constexpr int kRawB = 4 * 3 * HT * WD, kXsB = 4 * 3 * HT * kTileX, kUsB = 4 * 9 * UCELLS;
+    constexpr int kWrB = 4 * 4 * WCELLS, kFrB = kMasked ? 4 * WCELLS * (int)sizeof(FrT) : 4;
+    constexpr int kKrB = kStageK ? 4 * 3 * WCELLS : 4, kDqB = 4 * TY * kTileX, kLamB = 4 * 2 * kMaxStructs;
+    constexpr int oXs = kRawB, oUs = oXs + kXsB, oWr = oUs + kUsB, oFr = oWr + kWrB;
+    constexpr int oKr = oFr + ((kFrB + 3) & ~3), oDq = oKr + kKrB, oLam = oDq + kDqB, kLdsTotal = oLam + kLamB;
+    static_assert(kLdsTotal <= kLdsMax, "LDS budget of the step kernel");
+    __shared__ __attribute__((aligned(16))) char smem[kLdsTotal];
+    auto raw = reinterpret_cast<float(*)[HT][WD]>(smem);            // du on the tile + R halo
+    auto xs = reinterpret_cast<float(*)[HT][kTileX]>(smem + oXs);
+    auto Us = reinterpret_cast<float(*)[3][UCELLS]>(smem + oUs);    // u planes z-1..z+1,
+                                                                    // slot (p - z0 + 1) % 3
+    auto Wr = reinterpret_cast<float(*)[WCELLS]>(smem + oWr);       // I0~ planes, slot = plane & 3
+    auto Fr = reinterpret_cast<FrT(*)[WCELLS]>(smem + oFr);         // their stencil structure bits
+    auto Kr = reinterpret_cast<float(*)[WCELLS]>(smem + oKr);       // K~ where the bits are
+                                                                    // nonzero, slot = plane % 3
+    auto dq = reinterpret_cast<float(*)[kTileX]>(smem + oDq);       // squared metric terms of the
+                                                                    // tile's voxels
+    auto lamt = reinterpret_cast<float(*)[kMaxStructs]>(smem + oLam);  // lambda_i; the sum of the
+                                                                       // other weights
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
@@ -759,6 +784,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < nx && gy < ny;
     const int ntx = (nx + kTileX - 1) / kTileX;
+    const int cbase = (ty + 1) * UW + tx + 1;  // this voxel's cell in a u ring plane
     float last[3] = {0.f, 0.f, 0.f};
     int prev = -1;
     if (kMasked && tid < kMaxStructs) {  // (the weights past k are zero; adding a zero is exact)
@@ -882,21 +908,21 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                 for (int m = 1; m <= R; ++m) t = __builtin_fmaf(wz[m], ring[k][R - m] + ring[k][R + m], t);
                 s[k] = t;
             }
-            const Split sx = split_axis(gx, s[0], nx);
-            const Split sy = split_axis(gy, s[1], ny);
-            const Split sz = split_axis(z, s[2], nz);
-            // lower corner offsets from the voxel; with each in {-1, 0} all corners lie in the
-            // ring.  The ring holds a one-cell halo staged at clamped coordinates, so the upper
-            // corner along each axis is the next column, row or plane of the ring even where
-            // the sample index was clamped (it holds the same value).
-            const int ox0 = sx.i0 - gx, oy0 = sy.i0 - gy, oz0 = sz.i0 - z;
-            const bool near = ox0 >= -1 && ox0 <= 0 && oy0 >= -1 && oy0 <= 0 && oz0 >= -1 && oz0 <= 0;
+            // lower corner of the sample x + s relative to the voxel: with each offset in
+            // {-1, 0} every corner lies in the ring.  The ring holds a one-cell halo staged at
+            // clamped coordinates, so where the sample leaves the volume the two corners along
+            // that axis hold the same value, their interpolation returns it exactly, and the
+            // result equals the clamped sample (split_axis) without any clamping here.
+            const float fx = floorf(s[0]), fy = floorf(s[1]), fz = floorf(s[2]);
+            const bool near = __builtin_fabsf(fx + 0.5f) <= 0.5f && __builtin_fabsf(fy + 0.5f) <= 0.5f &&
+                              __builtin_fabsf(fz + 0.5f) <= 0.5f;  // (NaN: not near)
             if (near) {
-                // ring cells: the plane's slot base (uniform), the row and the column
+                // ring cells: the plane's slot base (uniform), then the row and column offset
                 const int zs_m = ((z - z0) % 3) * UCELLS, zs_0 = ((z - z0 + 1) % 3) * UCELLS;
                 const int zs_p = ((z - z0 + 2) % 3) * UCELLS;
-                const int cell = (ty + 1 + oy0) * UW + tx + 1 + ox0;
-                const int i0 = (oz0 < 0 ? zs_m : zs_0) + cell, i1 = (oz0 < 0 ? zs_0 : zs_p) + cell;
+                const int cell = cbase + (int)__builtin_fmaf(fy, (float)UW, fx);
+                const int i0 = (fz < 0.f ? zs_m : zs_0) + cell, i1 = (fz < 0.f ? zs_0 : zs_p) + cell;
+                const float tx_ = s[0] - fx, ty_ = s[1] - fy, tz_ = s[2] - fz;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const float *U = &Us[k][0][0];
@@ -909,10 +935,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                     f[5] = U[i1 + 1];
                     f[6] = U[i1 + UW];
                     f[7] = U[i1 + UW + 1];
-                    stg(a.uc[k], v, s[k] + lerp8(f, sx.t, sy.t, sz.t));
+                    stg(a.uc[k], v, s[k] + lerp8(f, tx_, ty_, tz_));
                 }
             } else {
-                const Corners q = corners(sx, sy, sz, nx, nxy);
+                const Corners q = corners(split_axis(gx, s[0], nx), split_axis(gy, s[1], ny),
+                                          split_axis(z, s[2], nz), nx, nxy);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) stg(a.uc[k], v, s[k] + trilinear(a.u[k], q));
             }

@@ -929,13 +929,14 @@ struct Job {
         sa.partials = metric() ? partials : nullptr;
         sa.d = d;
         sa.k = contour ? k : 0;
-        sa.lam_sum = 0.f;
+        float lam_sum = 0.f;
         sa.neg = 0;
         for (int i = 0; i < kMaxStructs; ++i) {
             sa.lam[i] = i < k ? lam[i] : 0.f;
             if (i < k && hs[i] < 0.f) sa.neg |= 1u << i;
-            if (i < sa.k) sa.lam_sum += sa.lam[i];
+            if (i < sa.k) lam_sum += sa.lam[i];
         }
+        sa.far_l1 = 1.f + lam_sum;
         sa.c0 = req.params.intensity_offset;
         sa.inv_norm = 1.0f / req.params.norm_range;
         for (int m = 0; m <= kMaxRadius; ++m) {
@@ -944,6 +945,10 @@ struct Job {
         }
         sa.gs[0] = gs[level][0];
         sa.gs[1] = gs[level][2];
+        sa.gs2[0] = sa.gs[0] * sa.gs[0];
+        sa.gs2[1] = sa.gs[1] * sa.gs[1];
+        sa.far_cx = 2.f * sa.gs2[0] * sa.far_l1;
+        sa.far_cz = 2.f * sa.gs2[1] * sa.far_l1;
         sa.tz = ctx->tune.step_tz;
         sa.stop = delta_on ? stop_dev : nullptr;
         sa.iter = iter;

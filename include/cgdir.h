@@ -185,15 +185,23 @@ typedef struct cgdir_request {
 } cgdir_request;
 
 /* Register n pairs of uneven sizes and structure counts together on the device
- * (blocking): every iteration phase runs once for all pairs that still have work.
+ * (blocking): every iteration phase runs once for all pairs of a group that still have work;
+ * the pairs are grouped by their Gaussian radii, and the groups run on two streams of the
+ * context that share the device.
  * Each pair's result equals what cgdir_register returns for it alone.  status (host,
  * n entries, may be NULL) receives each pair's code.  Returns the first failing code.
  * Errors: as cgdir_register; CGDIR_E_NOMEM when the pool cannot hold all pairs at once. */
 int cgdir_register_batch(cgdir_ctx *ctx, int n, const cgdir_request *reqs, int *status);
 
 /* Serving: queue a request, non-blocking.  Requests are admitted in arrival order when a
- * slot is free and the pool holds their footprint; admitted requests advance together,
- * iteration by iteration, and new ones join between iterations (continuous batching).
+ * slot is free and the pool holds their footprint, and new ones join between iterations
+ * (continuous batching).  Admitted requests advance iteration by iteration in lockstep groups,
+ * their launches merged, on two streams of the context that share the device: the small
+ * requests (finest level below 8 M voxels) in one, the large ones in the other, so that a small
+ * request does not advance at the pace of a large one's launches; while no request waits for
+ * admission the large ones run one at a time, oldest first, and while requests wait all run
+ * together.  Device inputs the caller ordered on the context stream before the call are
+ * complete before the request reads them.
  * Returns CGDIR_E_NOMEM at once if the footprint exceeds the whole pool, CGDIR_E_INVAL
  * for invalid arguments.  *ticket identifies the request.  A context keeps the status of
  * its CGDIR_KEEP_FINISHED most recently finished requests (done, failed or cancelled); an

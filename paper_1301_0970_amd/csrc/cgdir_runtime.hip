@@ -194,12 +194,13 @@ const char *kKernelNames[K_COUNT] = {"step", "smooth", "delta", "restrict", "pro
 
 // ------------------------------------------------------------------ tile autotuner
 // A pair's results do not depend on the tile shape of any kernel, so the first launches of
-// each group rotate through candidate shapes, each timed with HIP events on the stream; once
-// every candidate has been timed, the fastest (per voxel of its launch) is kept for the group
-// for the rest of the context's life.  A group is (kernel, radius, dims of the launch's
-// largest pair, log2 of the launch's voxel count): launches that mix different pairs, as
-// served requests join and leave, fall into few groups, while a launch of many small pairs
-// is still tuned apart from one small pair alone.  CGDIR_TUNE fixes the shapes instead.
+// each group rotate through candidate shapes, each timed with HIP events on the stream.  One
+// timing of a launch varies by a few per cent from the next, so the three fastest candidates
+// of that first round are timed twice more, and the group keeps the finalist with the least
+// median time per voxel for the rest of the context's life.  A group is (kernel, radius, dims
+// of the launch's largest pair, log2 of the launch's voxel count): launches that mix different
+// pairs, as served requests join and leave, fall into few groups, while a launch of many small
+// pairs is still tuned apart from one small pair alone.  CGDIR_TUNE fixes the shapes instead.
 struct TileCfg {
     int ty, tz;
 };
@@ -215,22 +216,43 @@ class Tuner {
     TileCfg fixed_step{8, 32}, fixed_smooth{8, 32};
     bool log = false;
 
+    static constexpr int kFinalists = 3, kRepeats = 3;
+    static int ncands(bool step)
+    {
+        return step ? (int)(sizeof(kStepCands) / sizeof(TileCfg)) : (int)(sizeof(kSmoothCands) / sizeof(TileCfg));
+    }
+
     // shape to use for the next launch of group `key`; *measure >= 0 asks the caller to time
     // the launch with events ev[0], ev[1] and hand them back through record()
     TileCfg choose(bool step, const std::string &key, int *measure)
     {
         *measure = -1;
         const TileCfg *c = step ? kStepCands : kSmoothCands;
-        const int nc = step ? (int)(sizeof(kStepCands) / sizeof(TileCfg)) : (int)(sizeof(kSmoothCands) / sizeof(TileCfg));
+        const int nc = ncands(step);
         if (!enabled) return step ? fixed_step : fixed_smooth;
         Entry &e = table_[key];
-        if (e.ms.empty()) e.ms.assign(nc, -1.f);
+        if (e.ms.empty()) e.ms.assign(nc, {});
         if (settle_if_measured(key, e)) return c[e.best];
-        if (e.next < nc) {
+        if (e.next < nc) {  // first round: every candidate once
             *measure = e.next;
             return c[e.next++];
         }
-        return c[0];
+        if (e.finalists.empty()) {  // the fastest few of the first round (waiting for its timings)
+            for (const Pending &p : e.pending) (void)hipEventSynchronize(p.b);
+            poll(e);
+            std::vector<int> order(nc);
+            for (int i = 0; i < nc; ++i) order[i] = i;
+            auto first = [&](int x) { return e.ms[x].empty() ? 1e30f : e.ms[x][0]; };  // (untimed: last)
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return first(x) < first(y); });
+            e.finalists.assign(order.begin(), order.begin() + std::min(kFinalists, nc));
+        }
+        const int extra = (int)e.finalists.size() * (kRepeats - 1);
+        if (e.fnext < extra) {  // the finalists again, in turn
+            *measure = e.finalists[e.fnext % e.finalists.size()];
+            ++e.fnext;
+            return c[*measure];
+        }
+        return c[e.finalists[0]];
     }
     // settled groups as "<group> <ty> <tz>" lines (groups whose candidates have all been
     // timed settle here too)
@@ -258,9 +280,7 @@ class Tuner {
     void settle(const std::string &key, int cand)
     {
         Entry &e = table_[key];
-        const int nc = key[0] == 'U' ? (int)(sizeof(kStepCands) / sizeof(TileCfg))
-                                     : (int)(sizeof(kSmoothCands) / sizeof(TileCfg));
-        if (e.ms.empty()) e.ms.assign(nc, -1.f);
+        if (e.ms.empty()) e.ms.assign(ncands(key[0] == 'U'), {});
         e.best = cand;
     }
     void record(const std::string &key, int cand, hipEvent_t a, hipEvent_t b, double voxels)
@@ -298,32 +318,41 @@ class Tuner {
         double scale;  // to ms per million voxels of the launch
     };
     struct Entry;
-    // true once the group has a shape: imported, or chosen now that every candidate's timing
-    // has landed (the fastest per voxel)
+    static float median(std::vector<float> v)
+    {
+        if (v.empty()) return 1e30f;
+        std::sort(v.begin(), v.end());
+        return v[v.size() / 2];
+    }
+    // true once the group has a shape: imported, or chosen now that every finalist's timings
+    // have landed (the least median time per voxel)
     bool settle_if_measured(const std::string &key, Entry &e)
     {
         if (e.best >= 0) return true;
-        if (e.ms.empty()) return false;
+        if (e.ms.empty() || e.finalists.empty()) return false;
         poll(e);
-        for (float m : e.ms)
-            if (m < 0.f) return false;
+        // (every repeat asked for has landed; a timing that could not be taken is just absent)
+        if (e.fnext < (int)e.finalists.size() * (kRepeats - 1) || !e.pending.empty()) return false;
         const bool step = key[0] == 'U';
         const TileCfg *c = step ? kStepCands : kSmoothCands;
-        const int nc = (int)e.ms.size();
-        e.best = 0;
-        for (int i = 1; i < nc; ++i)
-            if (e.ms[i] < e.ms[e.best]) e.best = i;
+        e.best = e.finalists[0];
+        for (int f : e.finalists)
+            if (median(e.ms[f]) < median(e.ms[e.best])) e.best = f;
         if (log) {
-            std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.5f ms per Mvoxel) |", key.c_str(), c[e.best].ty,
-                         c[e.best].tz, e.ms[e.best]);
-            for (int i = 0; i < nc; ++i) std::fprintf(stderr, " %d,%d:%.5f", c[i].ty, c[i].tz, e.ms[i]);
+            std::fprintf(stderr, "cgdir tune %s -> ty %d tz %d (%.5f ms per Mvoxel, median) |", key.c_str(),
+                         c[e.best].ty, c[e.best].tz, median(e.ms[e.best]));
+            for (size_t i = 0; i < e.ms.size(); ++i) {
+                std::fprintf(stderr, " %d,%d:", c[i].ty, c[i].tz);
+                for (float m : e.ms[i]) std::fprintf(stderr, "%.5f/", m);
+            }
             std::fprintf(stderr, "\n");
         }
         return true;
     }
     struct Entry {
-        int next = 0, best = -1;
-        std::vector<float> ms;
+        int next = 0, best = -1, fnext = 0;
+        std::vector<std::vector<float>> ms;   // timings of each candidate (ms per Mvoxel)
+        std::vector<int> finalists;
         std::vector<Pending> pending;
     };
     void poll(Entry &e)
@@ -332,8 +361,8 @@ class Tuner {
             Pending &p = e.pending[i];
             if (hipEventQuery(p.b) == hipSuccess) {
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) e.ms[p.cand] = (float)(ms * p.scale);
-                else e.ms[p.cand] = 1e30f;
+                if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) e.ms[p.cand].push_back((float)(ms * p.scale));
+                else e.ms[p.cand].push_back(1e30f);
                 spare_.push_back(p.a);
                 spare_.push_back(p.b);
                 e.pending.erase(e.pending.begin() + i);
@@ -364,6 +393,21 @@ struct cgdir_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // Lanes: streams of batched and served work, created with the context.  A batch runs its
+    // pairs in up to two lockstep groups on the two whole-device streams; the serving loop runs
+    // its requests on the whole device, or, while large and small requests are admitted
+    // together, the large ones on lane_major and the small ones on lane_minor, two streams
+    // restricted to complementary sets of compute units (minor_cus of them for the small ones).
+    hipStream_t lane_full[2] = {nullptr, nullptr};
+    hipStream_t lane_major = nullptr, lane_minor = nullptr;
+    int minor_cus = 0;          // 0: no partitioning (the masked streams are absent)
+    int batch_lanes = 2;
+    int serve_policy = 3;       // lanes of the serving loop: 0 one lockstep group on the whole
+                                // device; 1 large and small requests on the CU partition; 2 large
+                                // and small requests on the two whole-device streams; 3 as 2, with
+                                // the large requests one at a time, oldest first, unless requests
+                                // are waiting for admission
+    int64_t large_voxels = int64_t(8) << 20;   // finest-level voxels of a large request
     void *own_pool = nullptr;
     Pool pool;
     int max_slots = 1;
@@ -456,19 +500,19 @@ void drain_profile(cgdir_ctx *c)  // caller holds prof_mu
     c->pending.clear();
 }
 
-// Runs `fn` (one kernel launch) on the context stream, bracketed by events when profiling;
+// Runs `fn` (one kernel launch on stream s), bracketed by events on s when profiling;
 // `slot` = kernel id * 8 + pyramid level (7 for set-up work).
 template <typename F>
-hipError_t timed(cgdir_ctx *c, int slot, double vox, F &&fn)
+hipError_t timed(cgdir_ctx *c, hipStream_t s, int slot, double vox, F &&fn)
 {
     if (!c->profile) return fn();
     std::lock_guard<std::mutex> g(c->prof_mu);
     if (c->pending.size() > 8192) drain_profile(c);
     hipEvent_t a = take_event(c), b = take_event(c);
     if (!a || !b) return fn();
-    const bool ra = hipEventRecord(a, c->stream) == hipSuccess;
+    const bool ra = hipEventRecord(a, s) == hipSuccess;
     hipError_t e = fn();
-    const bool rb = hipEventRecord(b, c->stream) == hipSuccess;
+    const bool rb = hipEventRecord(b, s) == hipSuccess;
     if (ra && rb) {
         c->pending.push_back({slot, a, b, vox});
     } else {  // (an unrecorded pair is not timed)
@@ -575,6 +619,8 @@ int check_request(const cgdir_request &r)
 
 struct Job {
     cgdir_ctx *ctx = nullptr;
+    hipStream_t st = nullptr;     // the stream of the job's device work (the context's, or a
+                                  // lane's when batched or served)
     cgdir_request req{};
     const uint8_t *tplanes[CGDIR_MAX_STRUCTS] = {};
     const uint8_t *mplanes[CGDIR_MAX_STRUCTS] = {};
@@ -625,6 +671,7 @@ struct Job {
     int init(cgdir_ctx *c, const cgdir_request &r)
     {
         ctx = c;
+        st = c->stream;
         CG_TRY(check_request(r));
         req = r;
         k = r.target_masks.k;
@@ -764,7 +811,7 @@ struct Job {
     // device setup: copies, mask bits, UROI, signs, pyramid, initial field
     int setup()
     {
-        hipStream_t s = ctx->stream;
+        hipStream_t s = st;
         const int64_t n0 = d0.n();
         if (host_images) {
             const hipMemcpyKind km = req.moving.where == CGDIR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -786,14 +833,14 @@ struct Job {
                 } else {
                     for (int i = 0; i < k; ++i) planes[i] = m.planes[i];
                 }
-                HIP_TRY(timed(ctx, K_PACK * 8 + 7, (double)n0, [&] { return launch_pack_masks(planes, k, n0, bits, s); }));
+                HIP_TRY(timed(ctx, st, K_PACK * 8 + 7, (double)n0, [&] { return launch_pack_masks(planes, k, n0, bits, s); }));
                 if (m.where == CGDIR_HOST) HIP_TRY(hipStreamSynchronize(s));  // staging reused next side
             }
-            HIP_TRY(timed(ctx, K_PACK * 8 + 7, (double)n0, [&] { return launch_brick_occupancy(mbits, d0, mocc, s); }));
+            HIP_TRY(timed(ctx, st, K_PACK * 8 + 7, (double)n0, [&] { return launch_brick_occupancy(mbits, d0, mocc, s); }));
             for (int l = 1; l < L; ++l) {  // coarse levels with contour terms
                 if (!contour_at(l)) continue;
                 const Dims dl = level_dims(d0, l);
-                HIP_TRY(timed(ctx, K_PACK * 8 + l, (double)dl.n(), [&] {
+                HIP_TRY(timed(ctx, st, K_PACK * 8 + l, (double)dl.n(), [&] {
                     hipError_t e = launch_level_bits(mbits, d0, l, mbitsL[l], dl, s);
                     if (e == hipSuccess) e = launch_level_bits(tbits, d0, l, tbitsL[l], dl, s);
                     if (e == hipSuccess) e = launch_brick_occupancy(mbitsL[l], dl, moccL[l], s);
@@ -805,7 +852,7 @@ struct Job {
         uint8_t *rowdist = (uint8_t *)ucbuf + n0;
         if (delta_on) {
             if (k > 0) {
-                HIP_TRY(timed(ctx, K_UROI * 8 + 7, (double)n0,
+                HIP_TRY(timed(ctx, st, K_UROI * 8 + 7, (double)n0,
                               [&] { return launch_uroi(tbits, d0, req.params.uroi_margin, rowdist, uroi, s); }));
             } else {
                 HIP_TRY(hipMemsetAsync(uroi, 1, n0, s));
@@ -842,7 +889,7 @@ struct Job {
             for (int img = 0; img < 2; ++img) {
                 const float *src = img == 0 ? I0[l - 1] : T0[l - 1];
                 float *dst = (float *)(img == 0 ? I0[l] : T0[l]);
-                HIP_TRY(timed(ctx, K_RESTRICT * 8 + l, (double)din.n(), [&] {
+                HIP_TRY(timed(ctx, st, K_RESTRICT * 8 + l, (double)din.n(), [&] {
                     hipError_t e = launch_restrict_pass(src, t1, din, 0, wr, Rr, s);
                     if (e == hipSuccess) e = launch_restrict_pass(t1, t2, dx, 1, wr, Rr, s);
                     if (e == hipSuccess) e = launch_restrict_pass(t2, dst, dy, 2, wr, Rr, s);
@@ -858,8 +905,9 @@ struct Job {
         } else {
             HIP_TRY(launch_fill(ubuf, 3 * n0, 0.f, s));
         }
-        HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
-        HIP_TRY(hipMemsetAsync(stop_dev, 0, sizeof(int), s));
+        // (fill kernels rather than memset nodes: a caller may capture this work in a graph)
+        HIP_TRY(launch_fill((float *)flag, 1, 0.f, s));
+        HIP_TRY(launch_fill((float *)stop_dev, 1, 0.f, s));
         return CGDIR_OK;
     }
 
@@ -895,13 +943,13 @@ struct Job {
             const Dims dc = level_dims(d0, level + 1);
             const float *uc[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
             float *uf[3] = {comp(ucbuf, 0), comp(ucbuf, 1), comp(ucbuf, 2)};
-            HIP_TRY(timed(ctx, K_PROLONG * 8 + level, (double)df.n(),
-                          [&] { return launch_prolong(uc, dc, uf, df, ctx->stream); }));
+            HIP_TRY(timed(ctx, st, K_PROLONG * 8 + level, (double)df.n(),
+                          [&] { return launch_prolong(uc, dc, uf, df, st); }));
             std::swap(ubuf, ucbuf);
         }
         const float *u3[3] = {comp(ubuf, 0), comp(ubuf, 1), comp(ubuf, 2)};
         const WarpArgs w = warp_args();
-        HIP_TRY(timed(ctx, K_WARP * 8 + level, (double)df.n(), [&] { return launch_warp_init(w, u3, ctx->stream); }));
+        HIP_TRY(timed(ctx, st, K_WARP * 8 + level, (double)df.n(), [&] { return launch_warp_init(w, u3, st); }));
         return CGDIR_OK;
     }
 
@@ -992,7 +1040,7 @@ struct Job {
     int end_level()
     {
         const Dims d = level_dims(d0, level);
-        for (int c = 0; c < 3; ++c) HIP_TRY(launch_nonfinite(comp(ubuf, c), d.n(), flag, ctx->stream));
+        for (int c = 0; c < 3; ++c) HIP_TRY(launch_nonfinite(comp(ubuf, c), d.n(), flag, st));
         return CGDIR_OK;
     }
 
@@ -1035,10 +1083,9 @@ struct Job {
                 last_delta = pin->delta;
             }
             if (!pin_busy && iter % req.params.stop_window == 0) {
-                HIP_TRY(hipMemcpyAsync(&pin->stop, stop_dev, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-                HIP_TRY(hipMemcpyAsync(&pin->delta, delta_dev + (iter - 1), sizeof(double), hipMemcpyDeviceToHost,
-                                       ctx->stream));
-                HIP_TRY(hipEventRecord(pin_ev, ctx->stream));
+                HIP_TRY(hipMemcpyAsync(&pin->stop, stop_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&pin->delta, delta_dev + (iter - 1), sizeof(double), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipEventRecord(pin_ev, st));
                 pin_busy = true;
             }
         }
@@ -1050,7 +1097,7 @@ struct Job {
     {
         const int64_t n0 = d0.n();
         const hipMemcpyKind kd = req.dvf_where == CGDIR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-        HIP_TRY(hipMemcpyAsync(req.dvf_out, ubuf, 3 * n0 * sizeof(float), kd, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(req.dvf_out, ubuf, 3 * n0 * sizeof(float), kd, st));
         return CGDIR_OK;
     }
 
@@ -1082,9 +1129,8 @@ struct Job {
 namespace cgdir {
 namespace {
 
-int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &codes)
+int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::vector<int> &codes)
 {
-    hipStream_t s = c->stream;
     std::vector<int> act;
     for (size_t i = 0; i < jobs.size(); ++i) {
         if (codes[i] != CGDIR_OK || jobs[i]->finished) continue;
@@ -1142,7 +1188,7 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
                 sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, cfg.ty, cfg.tz);
                 vox += (double)sb.d[q].d.n();
             }
-            HIP_TRY(timed(c, K_STEP * 8 + lvl, vox, [&] {
+            HIP_TRY(timed(c, s, K_STEP * 8 + lvl, vox, [&] {
                 return tuned(cand >= 0, key, cand, vox, [&] { return launch_step_batch(sb, g.first, cfg.ty, s); });
             }));
         }
@@ -1152,7 +1198,7 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
         for (size_t i = 0; i <= act.size(); ++i) {
             if (i < act.size() && jobs[act[i]]->metric()) db.d[db.n++] = jobs[act[i]]->delta_job();
             if (db.n > 0 && (db.n == kBatchDelta || i == act.size())) {
-                HIP_TRY(timed(c, K_DELTA * 8 + lvl, 0.0, [&] { return launch_delta_batch(db, s); }));
+                HIP_TRY(timed(c, s, K_DELTA * 8 + lvl, 0.0, [&] { return launch_delta_batch(db, s); }));
                 db.n = 0;
             }
         }
@@ -1172,13 +1218,73 @@ int run_tick(cgdir_ctx *c, const std::vector<Job *> &jobs, std::vector<int> &cod
                 sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, cfg.ty, cfg.tz);
                 vox += (double)sb.d[q].d.n();
             }
-            HIP_TRY(timed(c, K_SMOOTH * 8 + lvl, vox, [&] {
+            HIP_TRY(timed(c, s, K_SMOOTH * 8 + lvl, vox, [&] {
                 return tuned(cand >= 0, key, cand, vox, [&] { return launch_smooth_batch(sb, g.first, cfg.ty, s); });
             }));
         }
     }
     for (int i : act) codes[i] = jobs[i]->after_iteration();
     return CGDIR_OK;
+}
+
+// Lockstep groups of jobs, each on its own stream: the ticks of one group are ordered on its
+// stream, and the groups advance independently, each with at most two ticks queued ahead.
+struct LaneWork {
+    hipStream_t s = nullptr;
+    std::vector<Job *> jobs;
+    std::vector<int> codes;
+    std::deque<hipEvent_t> inflight;
+};
+
+bool lane_has_work(const LaneWork &L)
+{
+    for (size_t i = 0; i < L.jobs.size(); ++i)
+        if (L.codes[i] == CGDIR_OK && !L.jobs[i]->finished) return true;
+    return false;
+}
+
+// Runs every lane's jobs to completion.  The host issues a tick wherever a lane has fewer than
+// two queued and otherwise yields; a failed tick fails the jobs of its lane only.
+int drive_lanes(cgdir_ctx *c, std::vector<LaneWork> &lanes)
+{
+    std::vector<hipEvent_t> spare;
+    int rc = CGDIR_OK;
+    for (;;) {
+        bool any = false, issued = false;
+        for (LaneWork &L : lanes) {
+            while (!L.inflight.empty() && hipEventQuery(L.inflight.front()) != hipErrorNotReady) {
+                spare.push_back(L.inflight.front());  // (a device error surfaces at the final sync)
+                L.inflight.pop_front();
+            }
+            if (!lane_has_work(L)) continue;
+            any = true;
+            if (L.inflight.size() >= 2) continue;
+            const int t = run_tick(c, L.s, L.jobs, L.codes);
+            if (t != CGDIR_OK)
+                for (size_t i = 0; i < L.jobs.size(); ++i)
+                    if (L.codes[i] == CGDIR_OK && !L.jobs[i]->finished) L.codes[i] = t;
+            hipEvent_t e = nullptr;
+            if (!spare.empty()) {
+                e = spare.back();
+                spare.pop_back();
+            } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                e = nullptr;
+                rc = CGDIR_E_HIP;
+            }
+            if (e && hipEventRecord(e, L.s) == hipSuccess) L.inflight.push_back(e);
+            else if (e) spare.push_back(e);
+            issued = true;
+        }
+        if (!any) break;
+        if (!issued) std::this_thread::yield();
+    }
+    for (LaneWork &L : lanes)
+        for (hipEvent_t e : L.inflight) {
+            (void)hipEventSynchronize(e);
+            spare.push_back(e);
+        }
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+    return rc;
 }
 
 }  // namespace
@@ -1195,7 +1301,13 @@ struct cgdir_ctx::Request {
     int level = 0, iter = 0;   // progress mirrored for cgdir_poll (under ctx->mu)
     double last_delta = 0.0;
     hipEvent_t done_ev = nullptr;
+    hipEvent_t ready_ev = nullptr;  // recorded on the context stream at submission: the inputs
+                                    // the caller ordered before it are complete past it
     bool emitted = false;
+    ~Request()
+    {
+        if (ready_ev) (void)hipEventDestroy(ready_ev);
+    }
 };
 
 namespace cgdir {
@@ -1216,10 +1328,21 @@ void finish_request(cgdir_ctx *c, cgdir_ctx::Request *r, int code)
     }
 }
 
-// The serving loop: FIFO admission by pool footprint and free slots, then ticks in which
-// every admitted request advances one iteration; a request that finishes is copied out
-// and its slot and memory are recycled once its completion event has fired.  Events used
-// here belong to this thread alone.
+// The serving loop.  Admission is FIFO by pool footprint and free slots.  Admitted requests
+// advance in lockstep ticks (one iteration each per tick, their launches merged), grouped into
+// lanes that each have their own stream and at most two ticks queued.  With the default policy
+// (3) the large requests (finest level of at least large_voxels) tick on one whole-device
+// stream and the small ones on the other, so that a small request does not advance at the pace
+// of a large one's launches (a small request's launches are latency-bound and share the device
+// well); while no request waits for admission the large ones run one at a time, oldest first
+// (as a serial queue would run them), and while requests wait every admitted request advances
+// (the merged launches give more registrations per second).  Policy 0 runs every request in one
+// lockstep group, 1 puts the two groups on streams restricted to complementary sets of compute
+// units, 2 is 3 without the one-at-a-time rule (CGDIR_SERVE_POLICY).  The grouping is decided
+// again whenever a request joins or leaves; a request that changes lanes has its next launches
+// ordered after its earlier ones by an event.  A request that finishes is copied out and its
+// slot and memory are recycled once its completion event has fired.  Events used here belong to
+// this thread alone.
 void scheduler(cgdir_ctx *c)
 {
     const bool device_ok = hipSetDevice(c->device) == hipSuccess;  // (else every request fails)
@@ -1234,12 +1357,41 @@ void scheduler(cgdir_ctx *c)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
         return e;
     };
+    struct Lane {
+        hipStream_t s;
+        std::deque<hipEvent_t> inflight;
+    };
+    const int policy = c->serve_policy == 1 && !(c->minor_cus > 0 && c->lane_major && c->lane_minor) ? 3 : c->serve_policy;
+    Lane lanes[3] = {{c->lane_full[0], {}}, {policy == 1 ? c->lane_major : c->lane_full[1], {}},
+                     {policy == 1 ? c->lane_minor : nullptr, {}}};
+    const bool can_split = policy != 0;
+    auto large = [&](const cgdir_ctx::Request *r) { return r->job.d0.n() >= c->large_voxels; };
     std::vector<cgdir_ctx::Request *> active;
-    std::deque<hipEvent_t> ticks;
+    // lane of each admitted request under the current mix: 0 whole device, 1 major, 2 minor
+    auto lane_of = [&](const cgdir_ctx::Request *r, bool split) {
+        if (!split) return 0;
+        return policy == 1 ? (large(r) ? 1 : 2) : (large(r) ? 0 : 1);  // (2 and 3)
+    };
+    auto mixed = [&]() {
+        bool any_large = false, any_small = false;
+        for (cgdir_ctx::Request *r : active)
+            if (!r->job.finished && r->error == CGDIR_OK) (large(r) ? any_large : any_small) = true;
+        return can_split && any_large && any_small;
+    };
+    // move a request's device work to stream `to`: its next launches follow its earlier ones
+    auto move_to = [&](cgdir_ctx::Request *r, hipStream_t to) {
+        if (r->job.st == to) return;
+        hipEvent_t e = get_ev();
+        bool ok = e && hipEventRecord(e, r->job.st) == hipSuccess && hipStreamWaitEvent(to, e, 0) == hipSuccess;
+        if (!ok) (void)hipStreamSynchronize(r->job.st);  // (ordered the slow way)
+        if (e) spare.push_back(e);  // (a wait captures the event's state when it is called)
+        r->job.st = to;
+    };
     for (;;) {
         // admission, in arrival order.  The request leaves the queue under mu; its set-up
         // launches run after mu is released, so that poll, submit and cancel never wait for
         // the launch lock (a blocking registration may hold it for a long time).
+        bool changed = false;
         for (;;) {
             cgdir_ctx::Request *r = nullptr;
             {
@@ -1262,19 +1414,24 @@ void scheduler(cgdir_ctx *c)
                 r->state = CGDIR_RUNNING;
                 r->t_admit = now_ns();
             }
-            int rc;
-            {
+            active.push_back(r);
+            // its set-up runs on the lane it joins, after the caller's inputs
+            r->job.st = lanes[lane_of(r, mixed())].s;
+            int rc = CGDIR_OK;
+            if (r->ready_ev && hipStreamWaitEvent(r->job.st, r->ready_ev, 0) != hipSuccess) rc = CGDIR_E_HIP;
+            if (rc == CGDIR_OK) {
                 std::lock_guard<std::mutex> lg(c->launch_mu);
                 rc = r->job.setup();
             }
             if (rc != CGDIR_OK) {
-                (void)hipStreamSynchronize(c->stream);  // set-up work in flight may still use its memory
+                (void)hipStreamSynchronize(r->job.st);  // set-up work in flight may still use its memory
+                active.pop_back();
                 std::lock_guard<std::mutex> lk(c->mu);
                 finish_request(c, r, rc);
                 c->cv.notify_all();
                 continue;
             }
-            active.push_back(r);
+            changed = true;
         }
         if (active.empty()) {
             std::unique_lock<std::mutex> lk(c->mu);
@@ -1282,78 +1439,111 @@ void scheduler(cgdir_ctx *c)
             c->cv.wait_for(lk, std::chrono::milliseconds(20));  // new work, or memory for the head
             continue;
         }
-        // one tick: every admitted request advances one iteration
+        bool backlog;  // requests wait for admission: throughput before the order of arrival
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            backlog = !c->queue.empty();
+        }
+        // the large request that runs while there is no backlog (policy 3): the oldest
+        const cgdir_ctx::Request *lead = nullptr;
+        if (policy == 3 && !backlog)
+            for (cgdir_ctx::Request *r : active)
+                if (!r->job.finished && r->error == CGDIR_OK && large(r)) {
+                    lead = r;
+                    break;
+                }
+        if (changed) {  // regroup: every running request onto its lane under the new mix
+            const bool split = mixed();
+            for (cgdir_ctx::Request *r : active)
+                if (!r->job.finished && r->error == CGDIR_OK) move_to(r, lanes[lane_of(r, split)].s);
+        }
+        // one tick on every lane that has running requests and fewer than two ticks queued
+        bool issued = false, ended = false;
         {
             std::lock_guard<std::mutex> lg(c->launch_mu);
-            std::vector<Job *> tj;
-            std::vector<cgdir_ctx::Request *> tr;
-            for (cgdir_ctx::Request *r : active)
-                if (!r->job.finished && r->error == CGDIR_OK) {
-                    tj.push_back(&r->job);
-                    tr.push_back(r);
+            for (Lane &L : lanes) {
+                while (!L.inflight.empty() && hipEventQuery(L.inflight.front()) != hipErrorNotReady) {
+                    spare.push_back(L.inflight.front());  // (a device error shows in the completion checks)
+                    L.inflight.pop_front();
                 }
-            std::vector<int> codes(tj.size(), CGDIR_OK);
-            const int rc = tj.empty() ? CGDIR_OK : run_tick(c, tj, codes);
-            for (size_t i = 0; i < tj.size(); ++i) {
-                const int code = rc != CGDIR_OK ? rc : codes[i];
-                if (code != CGDIR_OK) {
-                    tr[i]->job.finished = true;
-                    tr[i]->error = code;
+                if (!L.s || L.inflight.size() >= 2) continue;
+                std::vector<Job *> tj;
+                std::vector<cgdir_ctx::Request *> tr;
+                for (cgdir_ctx::Request *r : active)
+                    if (!r->job.finished && r->error == CGDIR_OK && r->job.st == L.s &&
+                        !(lead && large(r) && r != lead)) {  // (later large ones wait their turn)
+                        tj.push_back(&r->job);
+                        tr.push_back(r);
+                    }
+                if (tj.empty()) continue;
+                std::vector<int> codes(tj.size(), CGDIR_OK);
+                const int rc = run_tick(c, L.s, tj, codes);
+                for (size_t i = 0; i < tj.size(); ++i) {
+                    const int code = rc != CGDIR_OK ? rc : codes[i];
+                    if (code != CGDIR_OK) {
+                        tr[i]->job.finished = true;
+                        tr[i]->error = code;
+                    }
                 }
+                hipEvent_t te = get_ev();
+                if (te) {
+                    if (hipEventRecord(te, L.s) == hipSuccess) L.inflight.push_back(te);
+                    else spare.push_back(te);
+                }
+                issued = true;
             }
             for (cgdir_ctx::Request *r : active) {
                 if (r->job.finished && !r->emitted) {
                     if (r->error == CGDIR_OK) r->error = r->job.emit();
                     r->done_ev = get_ev();
-                    if (r->done_ev && hipEventRecord(r->done_ev, c->stream) != hipSuccess) {
+                    if (r->done_ev && hipEventRecord(r->done_ev, r->job.st) != hipSuccess) {
                         spare.push_back(r->done_ev);  // (completion then found by a stream sync)
                         r->done_ev = nullptr;
                     }
                     r->emitted = true;
+                    ended = true;
                 }
             }
-            hipEvent_t te = get_ev();
-            if (te) {
-                if (hipEventRecord(te, c->stream) == hipSuccess) ticks.push_back(te);
-                else spare.push_back(te);
-            }
-        }
-        while (ticks.size() > 2) {  // bounded look-ahead of queued ticks
-            // (an error here is the device's; the next launches and the completion checks
-            // below report it)
-            (void)hipEventSynchronize(ticks.front());
-            spare.push_back(ticks.front());
-            ticks.pop_front();
         }
         // progress and completions
-        std::lock_guard<std::mutex> lk(c->mu);
-        for (size_t i = 0; i < active.size();) {
-            cgdir_ctx::Request *r = active[i];
-            r->level = r->job.level;
-            r->iter = r->job.iter;
-            r->last_delta = r->job.last_delta;
-            const hipError_t q = r->emitted && r->done_ev ? hipEventQuery(r->done_ev) : hipSuccess;
-            if (r->emitted && q != hipErrorNotReady) {
-                // no event: wait for its copies; a failed query or sync (a device error) fails
-                // the request instead of leaving it pending
-                hipError_t e = q;
-                if (!r->done_ev) e = hipStreamSynchronize(c->stream);
-                if (e != hipSuccess && r->error == CGDIR_OK) r->error = CGDIR_E_HIP;
-                const int rc = r->error != CGDIR_OK ? r->error : r->job.conclude();
-                if (r->done_ev) spare.push_back(r->done_ev);
-                r->done_ev = nullptr;
-                finish_request(c, r, rc);
-                active.erase(active.begin() + i);
-                c->cv.notify_all();
-            } else {
-                ++i;
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            for (size_t i = 0; i < active.size();) {
+                cgdir_ctx::Request *r = active[i];
+                r->level = r->job.level;
+                r->iter = r->job.iter;
+                r->last_delta = r->job.last_delta;
+                const hipError_t q = r->emitted && r->done_ev ? hipEventQuery(r->done_ev) : hipSuccess;
+                if (r->emitted && q != hipErrorNotReady) {
+                    // no event: wait for its copies; a failed query or sync (a device error) fails
+                    // the request instead of leaving it pending
+                    hipError_t e = q;
+                    if (!r->done_ev) e = hipStreamSynchronize(r->job.st);
+                    if (e != hipSuccess && r->error == CGDIR_OK) r->error = CGDIR_E_HIP;
+                    const int rc = r->error != CGDIR_OK ? r->error : r->job.conclude();
+                    if (r->done_ev) spare.push_back(r->done_ev);
+                    r->done_ev = nullptr;
+                    finish_request(c, r, rc);
+                    active.erase(active.begin() + i);
+                    c->cv.notify_all();
+                    ended = true;
+                } else {
+                    ++i;
+                }
             }
         }
+        if (ended) {  // a request left: regroup the rest
+            const bool split = mixed();
+            for (cgdir_ctx::Request *r : active)
+                if (!r->job.finished && r->error == CGDIR_OK) move_to(r, lanes[lane_of(r, split)].s);
+        }
+        if (!issued && !ended) std::this_thread::yield();
     }
-    for (hipEvent_t e : ticks) {
-        (void)hipEventSynchronize(e);
-        spare.push_back(e);
-    }
+    for (Lane &L : lanes)
+        for (hipEvent_t e : L.inflight) {
+            (void)hipEventSynchronize(e);
+            spare.push_back(e);
+        }
     for (hipEvent_t e : spare) (void)hipEventDestroy(e);
 }
 
@@ -1444,10 +1634,46 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
         if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return CGDIR_E_HIP;
         c->own_stream = true;
     }
+    auto drop_streams = [&]() {
+        for (hipStream_t &ls : c->lane_full)
+            if (ls) (void)hipStreamDestroy(ls);
+        if (c->lane_major) (void)hipStreamDestroy(c->lane_major);
+        if (c->lane_minor) (void)hipStreamDestroy(c->lane_minor);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    };
+    for (hipStream_t &ls : c->lane_full)
+        if (hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) != hipSuccess) {
+            ls = nullptr;
+            drop_streams();
+            return CGDIR_E_HIP;
+        }
+    if (const char *e = std::getenv("CGDIR_BATCH_LANES")) c->batch_lanes = std::max(1, std::min(2, std::atoi(e)));
+    if (const char *e = std::getenv("CGDIR_SERVE_LARGE")) c->large_voxels = std::max<int64_t>(1, std::atoll(e));
+    if (const char *e = std::getenv("CGDIR_SERVE_POLICY")) c->serve_policy = std::max(0, std::min(3, std::atoi(e)));
+    {
+        // the CU partition of the serving loop: the last minor CUs for small requests
+        int ncu = 0;
+        int minor = 32;
+        if (const char *e = std::getenv("CGDIR_SERVE_SPLIT")) minor = std::atoi(e);
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, desc->device) == hipSuccess &&
+            minor > 0 && minor < ncu && ncu <= 32 * 16) {
+            uint32_t maj[16] = {}, mnr[16] = {};
+            const int words = (ncu + 31) / 32;
+            for (int cu = 0; cu < ncu; ++cu) (cu < ncu - minor ? maj : mnr)[cu / 32] |= 1u << (cu % 32);
+            if (hipExtStreamCreateWithCUMask(&c->lane_major, words, maj) == hipSuccess &&
+                hipExtStreamCreateWithCUMask(&c->lane_minor, words, mnr) == hipSuccess) {
+                c->minor_cus = minor;
+            } else {  // (no partitioning: every served request runs on the whole device)
+                if (c->lane_major) (void)hipStreamDestroy(c->lane_major);
+                c->lane_major = c->lane_minor = nullptr;
+                (void)hipGetLastError();
+            }
+        }
+    }
     void *pool = desc->pool;
     if (!pool) {
         if (hipMalloc(&c->own_pool, desc->pool_bytes) != hipSuccess) {
-            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            drop_streams();
             return CGDIR_E_NOMEM;
         }
         pool = c->own_pool;
@@ -1474,6 +1700,8 @@ int cgdir_destroy(cgdir_ctx *c)
     c->cv.notify_all();
     if (c->sched_started) c->sched.join();
     (void)hipStreamSynchronize(c->stream);
+    for (hipStream_t ls : {c->lane_full[0], c->lane_full[1], c->lane_major, c->lane_minor})
+        if (ls) (void)hipStreamSynchronize(ls);
     {
         std::lock_guard<std::mutex> g(c->prof_mu);
         drain_profile(c);
@@ -1486,6 +1714,11 @@ int cgdir_destroy(cgdir_ctx *c)
     }
     for (PinRec *chunk : c->pin_chunks) (void)hipHostFree(chunk);
     if (c->own_pool) (void)hipFree(c->own_pool);
+    for (hipStream_t ls : {c->lane_full[0], c->lane_full[1], c->lane_major, c->lane_minor})
+        if (ls) {
+            (void)hipStreamSynchronize(ls);
+            (void)hipStreamDestroy(ls);
+        }
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return CGDIR_OK;
@@ -1516,7 +1749,7 @@ int cgdir_register(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume 
         std::vector<Job *> jobs{&job};
         std::vector<int> codes{rc};
         while (codes[0] == CGDIR_OK && !job.finished) {
-            const int t = run_tick(c, jobs, codes);
+            const int t = run_tick(c, c->stream, jobs, codes);
             if (t != CGDIR_OK) codes[0] = t;
         }
         rc = codes[0];
@@ -1553,23 +1786,64 @@ int cgdir_register_batch(cgdir_ctx *c, int n, const cgdir_request *reqs, int *st
             return CGDIR_E_NOMEM;
         }
     {
-        std::lock_guard<std::mutex> lg(c->launch_mu);
+        // lanes: the pairs grouped by their Gaussian radii (the launches of one tick are per
+        // radius anyway), the groups spread over the two whole-device lane streams, heaviest
+        // first onto the lighter lane; with one group and two lanes the pairs themselves are
+        // spread that way.  Every lane first waits for the caller's order on the context stream.
+        std::map<std::pair<int, int>, std::vector<int>> groups;
         for (int i = 0; i < n; ++i)
-            if (st[i] == CGDIR_OK) st[i] = jobs[i]->setup();
-        std::vector<Job *> jp;
-        for (auto &j : jobs) jp.push_back(j.get());
-        for (;;) {  // one iteration of every unfinished pair per tick
-            bool more = false;
-            for (int i = 0; i < n; ++i) more = more || (st[i] == CGDIR_OK && !jobs[i]->finished);
-            if (!more) break;
-            const int t = run_tick(c, jp, st);
-            if (t != CGDIR_OK)
-                for (int i = 0; i < n; ++i)
-                    if (st[i] == CGDIR_OK && !jobs[i]->finished) st[i] = t;
+            if (st[i] == CGDIR_OK) groups[{jobs[i]->Rf[0], jobs[i]->Rd[0]}].push_back(i);
+        const int nl = std::min<int>(c->batch_lanes, std::max<int>(1, n));
+        std::vector<std::vector<int>> units;
+        if (groups.size() == 1 && nl > 1) {
+            for (int i : groups.begin()->second) units.push_back({i});
+        } else {
+            for (auto &g : groups) units.push_back(g.second);
         }
+        auto work = [&](const std::vector<int> &u) {
+            double w = 0.0;
+            for (int i : u) w += (double)jobs[i]->d0.n();
+            return w;
+        };
+        std::stable_sort(units.begin(), units.end(),
+                         [&](const std::vector<int> &a, const std::vector<int> &b) { return work(a) > work(b); });
+        std::vector<LaneWork> lanes(nl);
+        std::vector<double> load(nl, 0.0);
+        std::vector<std::vector<int>> members(nl);
+        for (auto &u : units) {
+            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[l] += work(u);
+            for (int i : u) members[l].push_back(i);
+        }
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        hipEvent_t ready = nullptr;
+        if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ready, c->stream) != hipSuccess) {
+            if (ready) (void)hipEventDestroy(ready);
+            for (auto &j : jobs) j->release();
+            if (status)
+                for (int i = 0; i < n; ++i) status[i] = CGDIR_E_HIP;
+            return CGDIR_E_HIP;
+        }
+        for (int l = 0; l < nl; ++l) {
+            lanes[l].s = c->lane_full[l];
+            (void)hipStreamWaitEvent(lanes[l].s, ready, 0);
+            for (int i : members[l]) {
+                jobs[i]->st = lanes[l].s;
+                st[i] = jobs[i]->setup();
+                lanes[l].jobs.push_back(jobs[i].get());
+                lanes[l].codes.push_back(st[i]);
+            }
+        }
+        (void)hipEventDestroy(ready);  // (the waits captured it)
+        if (drive_lanes(c, lanes) != CGDIR_OK) first = CGDIR_E_HIP;
+        for (int l = 0; l < nl; ++l)
+            for (size_t q = 0; q < members[l].size(); ++q) st[members[l][q]] = lanes[l].codes[q];
         for (int i = 0; i < n; ++i)
             if (st[i] == CGDIR_OK) st[i] = jobs[i]->emit();
     }
+    for (hipStream_t ls : c->lane_full)
+        if (hipStreamSynchronize(ls) != hipSuccess) first = CGDIR_E_HIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) first = CGDIR_E_HIP;
     for (int i = 0; i < n; ++i) {
         if (st[i] == CGDIR_OK) st[i] = jobs[i]->conclude();
@@ -1617,7 +1891,7 @@ int cgdir_warp(cgdir_ctx *c, const cgdir_volume *src, const float *dvf, int mode
         o_dev = o;
     }
     const float *u3[3] = {u_dev, u_dev + n, u_dev + 2 * n};
-    hipError_t e = timed(c, K_WARP * 8 + 7, (double)n, [&] {
+    hipError_t e = timed(c, c->stream, K_WARP * 8 + 7, (double)n, [&] {
         return mode == CGDIR_WARP_LINEAR ? launch_warp_linear((const float *)s_dev, d, u3, (float *)o_dev, c->stream)
                                          : launch_warp_mask((const uint8_t *)s_dev, d, u3, (uint8_t *)o_dev, c->stream);
     });
@@ -1850,6 +2124,11 @@ int cgdir_submit(cgdir_ctx *c, const cgdir_request *req, uint64_t *ticket)
     CG_TRY(r->job.init(c, *req));
     if (r->job.need() > c->pool.size()) return CGDIR_E_NOMEM;
     r->t_submit = now_ns();
+    // the scheduler runs the request on its lane streams after this point of the context stream
+    if (hipSetDevice(c->device) != hipSuccess ||
+        hipEventCreateWithFlags(&r->ready_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(r->ready_ev, c->stream) != hipSuccess)
+        return CGDIR_E_HIP;
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->stopping) return CGDIR_E_INVAL;
     const uint64_t t = c->next_ticket++;

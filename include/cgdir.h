@@ -47,8 +47,13 @@ enum cgdir_code {
     CGDIR_E_CANCELLED = -6, /* the request was cancelled */
     CGDIR_E_NONFINITE = -7, /* the field or the metric became NaN/Inf */
     CGDIR_E_UNIMPL = -8,    /* a parameter combination that is not implemented */
-    CGDIR_E_TIMEOUT = -9    /* cgdir_wait timed out */
+    CGDIR_E_TIMEOUT = -9,   /* cgdir_wait timed out */
+    CGDIR_E_SCRATCH = -10   /* cgdir_register_static: the registration needs more device memory
+                               than the static scratch holds (CGDIR_STATIC_SCRATCH_BYTES) */
 };
+
+/* Device memory of cgdir_register_static, per device (bytes). */
+#define CGDIR_STATIC_SCRATCH_BYTES (64u << 20)
 
 enum cgdir_where { CGDIR_HOST = 0, CGDIR_DEVICE = 1 };
 enum cgdir_warp_mode { CGDIR_WARP_LINEAR = 0, CGDIR_WARP_MASK = 1 };
@@ -163,6 +168,26 @@ int cgdir_destroy(cgdir_ctx *ctx);
 int cgdir_register(cgdir_ctx *ctx, const cgdir_volume *target, const cgdir_volume *moving,
                    const cgdir_masks *target_masks, const cgdir_masks *moving_masks,
                    const cgdir_params *params, float *dvf_out, int dvf_where);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid it): cgdir_register on device buffers that allocates nothing.
+ * Its per-registration buffers come from a static device array of CGDIR_STATIC_SCRATCH_BYTES
+ * (64 MiB) that each device holds until the process ends, instead of the context pool; the
+ * context must have been created (cgdir_create looks the array up on its device) and its own
+ * stream runs the work.  The call creates no events and makes no memset: what must start at
+ * zero is cleared by fill kernels.  Every call on one device shares that device's array, which
+ * keeps the last call's contents; calls that overlap on one device would race, so the library
+ * runs them one at a time per device (a lock), and nothing else may use the array.
+ * Arguments as cgdir_register, with every buffer on the device (CGDIR_E_INVAL otherwise).
+ * Limits: about 36 bytes per voxel with contour terms (up to about 1.8 M voxels),
+ * CGDIR_E_SCRATCH beyond; the stopping rule, delta_hist and automatic signs (sign 0) need
+ * host records and copies and give CGDIR_E_UNIMPL.  Tile shapes are those the context's
+ * autotuner has settled for the launch's group (by earlier cgdir_register calls or
+ * cgdir_tuning_import), else the first candidate; no candidate is timed.  Results equal
+ * cgdir_register's bit for bit.  Blocking. */
+int cgdir_register_static(cgdir_ctx *ctx, const cgdir_volume *target, const cgdir_volume *moving,
+                          const cgdir_masks *target_masks, const cgdir_masks *moving_masks,
+                          const cgdir_params *params, float *dvf_out);
 
 /* Warp src with a field on src's grid: out(x) = src(x + dvf(x)), trilinear, sample
  * position clamped to the volume (the interpolation of section 2.2, kernel 4).

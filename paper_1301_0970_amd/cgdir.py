@@ -25,8 +25,9 @@ MAX_LEVELS = 6
 KEEP_FINISHED = 4096   # served requests whose final status a context keeps
 
 OK = 0
-E_INVAL, E_NOMEM, E_HIP, E_BUSY, E_NOTFOUND, E_CANCELLED, E_NONFINITE, E_UNIMPL, E_TIMEOUT = (
-    -1, -2, -3, -4, -5, -6, -7, -8, -9)
+E_INVAL, E_NOMEM, E_HIP, E_BUSY, E_NOTFOUND, E_CANCELLED, E_NONFINITE, E_UNIMPL, E_TIMEOUT, E_SCRATCH = (
+    -1, -2, -3, -4, -5, -6, -7, -8, -9, -10)
+STATIC_SCRATCH_BYTES = 64 << 20   # device memory of cgdir_register_static, per device
 HOST, DEVICE = 0, 1
 WARP_LINEAR, WARP_MASK = 0, 1
 QUEUED, RUNNING, DONE, FAILED, CANCELLED = 0, 1, 2, 3, 4
@@ -99,7 +100,8 @@ class kernel_stat(ctypes.Structure):
 SYMBOLS = ["cgdir_params_default", "cgdir_create", "cgdir_destroy", "cgdir_register",
            "cgdir_warp", "cgdir_register_batch", "cgdir_submit", "cgdir_poll", "cgdir_cancel",
            "cgdir_wait", "cgdir_footprint", "cgdir_strerror", "cgdir_kernel_stats",
-           "cgdir_eval_params_default", "cgdir_evaluate", "cgdir_tuning_export", "cgdir_tuning_import"]
+           "cgdir_eval_params_default", "cgdir_evaluate", "cgdir_tuning_export", "cgdir_tuning_import",
+           "cgdir_register_static"]
 
 
 class eval_params(ctypes.Structure):
@@ -155,6 +157,8 @@ def _load():
                                    ctypes.c_void_p, ctypes.c_int, P(eval_params), P(eval_result)]
     lib.cgdir_tuning_export.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_size_t)]
     lib.cgdir_tuning_import.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+    lib.cgdir_register_static.argtypes = [ctypes.c_void_p, P(volume), P(volume), P(masks), P(masks),
+                                          P(params), ctypes.c_void_p]
     for name in SYMBOLS:
         if name not in ("cgdir_params_default", "cgdir_footprint", "cgdir_strerror",
                         "cgdir_eval_params_default"):
@@ -199,6 +203,14 @@ def register(h, target: volume, moving: volume, target_masks: Optional[masks],
                               ctypes.byref(target_masks) if target_masks is not None else None,
                               ctypes.byref(moving_masks) if moving_masks is not None else None,
                               ctypes.byref(prm), ctypes.c_void_p(dvf_out), dvf_where)
+
+
+def register_static(h, target: volume, moving: volume, target_masks: Optional[masks],
+                    moving_masks: Optional[masks], prm: params, dvf_out: int) -> int:
+    return LIB.cgdir_register_static(h, ctypes.byref(target), ctypes.byref(moving),
+                                     ctypes.byref(target_masks) if target_masks is not None else None,
+                                     ctypes.byref(moving_masks) if moving_masks is not None else None,
+                                     ctypes.byref(prm), ctypes.c_void_p(dvf_out))
 
 
 def warp(h, src: volume, dvf: int, mode: int, out: int) -> int:
@@ -404,6 +416,27 @@ class Context:
         _check(rc, "cgdir_register")
         if delta:
             return out, [hist[i] for i in range(done.value)], done.value
+        return out
+
+    def register_static(self, target, moving, target_masks=None, moving_masks=None, prm=None, out=None,
+                        initial=None):
+        """cgdir_register_static: the registration on device tensors, its buffers in the
+        library's static device scratch instead of the pool (nothing is allocated)."""
+        torch = self._torch
+        prm = params.from_buffer_copy(prm) if prm is not None else params_default()
+        if out is None:
+            out = torch.empty((3,) + tuple(target.shape), dtype=torch.float32, device=target.device)
+        self._field(out, target, "the output field")
+        keep = []
+        if initial is not None:
+            self._field(initial, target, "the initial field")
+            prm.initial_dvf = initial.data_ptr()
+            prm.initial_dvf_where = self._where(initial)
+        tm = self.masks(target_masks, keep)
+        mm = self.masks(moving_masks, keep)
+        tv, mv = self.volume(target), self.volume(moving)
+        self._order()
+        _check(register_static(self.handle, tv, mv, tm, mm, prm, out.data_ptr()), "cgdir_register_static")
         return out
 
     def warp(self, src, dvf, mode=WARP_LINEAR, out=None):

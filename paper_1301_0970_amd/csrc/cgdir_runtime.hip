@@ -24,8 +24,32 @@
 #include "cgdir.h"
 #include "cgdir_internal.h"
 
+// Device memory of cgdir_register_static: every per-registration buffer of a registration that
+// may not allocate.  Each device the library runs on holds its own copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress returns for that device
+// (the array's name in host code is a host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[CGDIR_STATIC_SCRATCH_BYTES];
+
 namespace cgdir {
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                    // guards g_scratch
+void *g_scratch[kMaxDevices] = {};          // the device address of `scratch`, per device
+std::mutex g_static_mu[kMaxDevices];        // one static registration at a time per device
+
+// The address of `scratch` on `device` (which must be current), looked up once per device.
+void *scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) g_scratch[device] = p;
+        else (void)hipGetLastError();
+    }
+    return g_scratch[device];
+}
 
 int64_t now_ns()
 {
@@ -254,6 +278,15 @@ class Tuner {
         }
         return c[e.finalists[0]];
     }
+    // the settled shape of a group, else the first candidate: never asks for a timing
+    TileCfg settled_or_default(bool step, const std::string &key)
+    {
+        if (!enabled) return step ? fixed_step : fixed_smooth;
+        const TileCfg *c = step ? kStepCands : kSmoothCands;
+        auto it = table_.find(key);
+        if (it != table_.end() && settle_if_measured(key, it->second)) return c[it->second.best];
+        return c[0];
+    }
     // settled groups as "<group> <ty> <tz>" lines (groups whose candidates have all been
     // timed settle here too)
     std::string export_text()
@@ -408,6 +441,8 @@ struct cgdir_ctx {
                                 // the large requests one at a time, oldest first, unless requests
                                 // are waiting for admission
     int64_t large_voxels = int64_t(8) << 20;   // finest-level voxels of a large request
+    void *scratch = nullptr;    // this device's static scratch (cgdir_register_static), or null
+    PinRec *static_pin = nullptr;  // pinned record of cgdir_register_static
     void *own_pool = nullptr;
     Pool pool;
     int max_slots = 1;
@@ -502,10 +537,12 @@ void drain_profile(cgdir_ctx *c)  // caller holds prof_mu
 
 // Runs `fn` (one kernel launch on stream s), bracketed by events on s when profiling;
 // `slot` = kernel id * 8 + pyramid level (7 for set-up work).
+thread_local bool t_no_events = false;  // set during cgdir_register_static: create no HIP events
+
 template <typename F>
 hipError_t timed(cgdir_ctx *c, hipStream_t s, int slot, double vox, F &&fn)
 {
-    if (!c->profile) return fn();
+    if (!c->profile || t_no_events) return fn();
     std::lock_guard<std::mutex> g(c->prof_mu);
     if (c->pending.size() > 8192) drain_profile(c);
     hipEvent_t a = take_event(c), b = take_event(c);
@@ -711,8 +748,19 @@ struct Job {
         return CGDIR_OK;
     }
 
+    // with an arena (cgdir_register_static) buffers are carved from it in order, else from the
+    // context pool
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
+
     void *take(size_t bytes)
     {
+        if (arena) {
+            const size_t off = align_up(arena_used), sz = align_up(bytes ? bytes : 1);
+            if (off + sz > arena_size) return nullptr;
+            arena_used = off + sz;
+            return arena + off;
+        }
         void *p = ctx->pool.alloc(bytes);
         if (p) allocs.push_back(p);
         return p;
@@ -722,6 +770,7 @@ struct Job {
     {
         for (void *p : allocs) ctx->pool.release(p);
         allocs.clear();
+        arena_used = 0;
         if (pin_ev) {
             if (pin_busy) (void)hipEventSynchronize(pin_ev);  // no copy may land in a recycled record
             (void)hipEventDestroy(pin_ev);
@@ -1116,7 +1165,13 @@ struct Job {
         }
         if (req.params.iters_done) *req.params.iters_done = iters_done0;
         int bad = 0;
-        HIP_TRY(hipMemcpy(&bad, flag, sizeof(int), hipMemcpyDeviceToHost));
+        if (arena && ctx->static_pin) {  // through the context's pinned record: no staging copy
+            HIP_TRY(hipMemcpyAsync(&ctx->static_pin->stop, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            bad = ctx->static_pin->stop;
+        } else {
+            HIP_TRY(hipMemcpy(&bad, flag, sizeof(int), hipMemcpyDeviceToHost));
+        }
         return bad ? CGDIR_E_NONFINITE : CGDIR_OK;
     }
 };
@@ -1129,7 +1184,8 @@ struct Job {
 namespace cgdir {
 namespace {
 
-int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::vector<int> &codes)
+int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::vector<int> &codes,
+             bool settled_only = false)
 {
     std::vector<int> act;
     for (size_t i = 0; i < jobs.size(); ++i) {
@@ -1156,6 +1212,15 @@ int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::v
         return key;
     };
     // a launch, timed for the tuner when it asks
+    // settled_only: tile shapes the tuner has settled (else its first candidate), no timing
+    // events and no profiling events (cgdir_register_static creates no HIP objects)
+    auto pick = [&](bool step, const std::string &key, int *cand) {
+        if (settled_only) {
+            *cand = -1;
+            return c->tuner.settled_or_default(step, key);
+        }
+        return c->tuner.choose(step, key, cand);
+    };
     auto tuned = [&](bool measure_it, const std::string &key, int cand, double voxels, auto &&fn) -> hipError_t {
         if (!measure_it) return fn();
         hipEvent_t ea = c->tuner.event(), eb = c->tuner.event();
@@ -1180,13 +1245,17 @@ int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::v
             sb.n = (int)std::min<size_t>(kBatchStep, v.size() - b);
             const std::string key = shapes_key('U', g.first, &v[b], sb.n);
             int cand = -1;
-            const TileCfg cfg = c->tuner.choose(true, key, &cand);
+            const TileCfg cfg = pick(true, key, &cand);
             double vox = 0.0;
             for (int q = 0; q < sb.n; ++q) {
                 sb.d[q] = jobs[v[b + q]]->step_args();
                 sb.d[q].tz = cfg.tz;
                 sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, cfg.ty, cfg.tz);
                 vox += (double)sb.d[q].d.n();
+            }
+            if (settled_only) {
+                HIP_TRY(launch_step_batch(sb, g.first, cfg.ty, s));
+                continue;
             }
             HIP_TRY(timed(c, s, K_STEP * 8 + lvl, vox, [&] {
                 return tuned(cand >= 0, key, cand, vox, [&] { return launch_step_batch(sb, g.first, cfg.ty, s); });
@@ -1210,13 +1279,17 @@ int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::v
             sb.n = (int)std::min<size_t>(kBatchSmooth, v.size() - b);
             const std::string key = shapes_key('S', g.first, &v[b], sb.n);
             int cand = -1;
-            const TileCfg cfg = c->tuner.choose(false, key, &cand);
+            const TileCfg cfg = pick(false, key, &cand);
             double vox = 0.0;
             for (int q = 0; q < sb.n; ++q) {
                 sb.d[q] = jobs[v[b + q]]->smooth_args();
                 sb.d[q].tz = cfg.tz;
                 sb.prefix[q + 1] = sb.prefix[q] + tile_blocks(sb.d[q].d, cfg.ty, cfg.tz);
                 vox += (double)sb.d[q].d.n();
+            }
+            if (settled_only) {
+                HIP_TRY(launch_smooth_batch(sb, g.first, cfg.ty, s));
+                continue;
             }
             HIP_TRY(timed(c, s, K_SMOOTH * 8 + lvl, vox, [&] {
                 return tuned(cand >= 0, key, cand, vox, [&] { return launch_smooth_batch(sb, g.first, cfg.ty, s); });
@@ -1595,6 +1668,7 @@ const char *cgdir_strerror(int code)
     case CGDIR_E_NONFINITE: return "non-finite field";
     case CGDIR_E_UNIMPL: return "not implemented";
     case CGDIR_E_TIMEOUT: return "timed out";
+    case CGDIR_E_SCRATCH: return "the registration does not fit the static scratch of cgdir_register_static";
     default: return "unknown error";
     }
 }
@@ -1679,6 +1753,9 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
         pool = c->own_pool;
     }
     c->pool.init((char *)pool, desc->pool_bytes);
+    // set-up of cgdir_register_static (nothing is allocated in that call itself)
+    c->scratch = scratch_address(desc->device);
+    c->static_pin = c->take_pin();
     *out = c.release();
     return CGDIR_OK;
 }
@@ -1754,6 +1831,60 @@ int cgdir_register(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume 
         }
         rc = codes[0];
         if (rc == CGDIR_OK) rc = job.emit();
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == CGDIR_OK) rc = CGDIR_E_HIP;
+    if (rc == CGDIR_OK) rc = job.conclude();
+    job.release();
+    return rc;
+}
+
+int cgdir_register_static(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume *moving,
+                          const cgdir_masks *target_masks, const cgdir_masks *moving_masks,
+                          const cgdir_params *params, float *dvf_out)
+{
+    if (!c || !target || !moving || !params || !dvf_out) return CGDIR_E_INVAL;
+    // device buffers only (a host buffer would need a staging copy)
+    if (target->where != CGDIR_DEVICE || moving->where != CGDIR_DEVICE) return CGDIR_E_INVAL;
+    for (const cgdir_masks *m : {target_masks, moving_masks})
+        if (m && m->k > 0 && m->where != CGDIR_DEVICE) return CGDIR_E_INVAL;
+    if (params->initial_dvf && params->initial_dvf_where != CGDIR_DEVICE) return CGDIR_E_INVAL;
+    // what needs pinned host records, events or host copies of device reductions is not here
+    if (params->stop_mode != 0 || params->delta_hist) return CGDIR_E_UNIMPL;
+    const int k = target_masks ? target_masks->k : 0;
+    for (int i = 0; i < k && i < CGDIR_MAX_STRUCTS; ++i)
+        if (params->sign[i] == 0) return CGDIR_E_UNIMPL;
+    cgdir_request r{};
+    r.target = *target;
+    r.moving = *moving;
+    static const cgdir_masks none = {0, nullptr, CGDIR_DEVICE};
+    r.target_masks = target_masks ? *target_masks : none;
+    r.moving_masks = moving_masks ? *moving_masks : none;
+    r.params = *params;
+    r.dvf_out = dvf_out;
+    r.dvf_where = CGDIR_DEVICE;
+    if (c->device < 0 || c->device >= kMaxDevices || hipSetDevice(c->device) != hipSuccess) return CGDIR_E_HIP;
+    if (!c->scratch || !c->static_pin) return CGDIR_E_HIP;  // the set-up at cgdir_create failed
+    Job job;
+    CG_TRY(job.init(c, r));
+    if (job.need() > (size_t)CGDIR_STATIC_SCRATCH_BYTES) return CGDIR_E_SCRATCH;
+    std::lock_guard<std::mutex> dev_lock(g_static_mu[c->device]);  // the array is shared per device
+    job.arena = (char *)c->scratch;
+    job.arena_size = CGDIR_STATIC_SCRATCH_BYTES;
+    CG_TRY(job.allocate());  // (carves the arena: no allocation)
+    int rc;
+    {
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        t_no_events = true;
+        rc = job.setup();
+        std::vector<Job *> jobs{&job};
+        std::vector<int> codes{rc};
+        while (codes[0] == CGDIR_OK && !job.finished) {
+            const int t = run_tick(c, c->stream, jobs, codes, true);
+            if (t != CGDIR_OK) codes[0] = t;
+        }
+        rc = codes[0];
+        if (rc == CGDIR_OK) rc = job.emit();
+        t_no_events = false;
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess && rc == CGDIR_OK) rc = CGDIR_E_HIP;
     if (rc == CGDIR_OK) rc = job.conclude();

@@ -58,6 +58,10 @@ def test_strerror_and_codes():
     assert cgdir.strerror(0) == "ok"
     assert "pool" in cgdir.strerror(cgdir.E_NOMEM)
     assert cgdir.strerror(12345) == "unknown error"
+    assert "static scratch" in cgdir.strerror(cgdir.E_SCRATCH)
+    src = open(os.path.join(ROOT, "include", "cgdir.h")).read()
+    m = re.search(r"#define CGDIR_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == cgdir.STATIC_SCRATCH_BYTES
 
 
 def test_create_rejects_bad_descriptions():
@@ -70,6 +74,7 @@ def test_create_rejects_bad_descriptions():
     assert lib.cgdir_create(ctypes.byref(h), ctypes.byref(d)) == cgdir.E_INVAL
     assert lib.cgdir_destroy(None) == cgdir.E_INVAL
     assert lib.cgdir_register(None, None, None, None, None, None, None, 0) == cgdir.E_INVAL
+    assert lib.cgdir_register_static(None, None, None, None, None, None, None) == cgdir.E_INVAL
 
 
 # C struct of each ctypes mirror in the binding, and the binding's field names that differ

@@ -401,18 +401,23 @@ __global__ void __launch_bounds__(256) k_brick_occupancy(const uint8_t *__restri
 // ============================================================================
 // Separable Gaussian (kernel 1) of u_c into u, sampled, radius R = ceil(3 sigma),
 // normalised, clamped indices, followed by the warp of the moving image with the new u
-// (kernel 4 on images).  A block owns a 64 x TY column tile: each z plane (tile + R halo)
-// is staged in LDS, filtered along x then y, and pushed into a register ring of 2R+1
-// planes that the z pass reads.  The warp of plane z is issued after its store and
-// finished after the next plane has been filtered, so its gathers overlap the filtering.
+// (kernel 4 on images).  A block owns a 64 x TY column tile and marches through the planes
+// z0 - R .. z1 - 1 + R that its z pass needs (clamped: a plane past a volume end is the end
+// plane again).  Each plane goes through three stages, one block-wide step apart: (a) its
+// values (tile + R halo, prefetched into registers one step earlier) are stored into LDS, (b)
+// filtered along x into a second LDS buffer, (c) filtered along y and pushed into a register
+// ring of 2R + 1 planes that the z pass reads.  One step runs stage (a) of plane l, (b) of
+// plane l - 1 and (c) of plane l - 2 on double-buffered LDS, so a step needs one barrier and
+// its three stages' latencies overlap.  The warp of an output plane is issued after the plane's
+// store and finished one step later, so its gathers overlap the next step's filtering.
 // ============================================================================
 template <int R, int TY>
 __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
 {
     constexpr int WD = kTileX + 2 * R, HT = TY + 2 * R, NT = kTileX * TY;
     constexpr int CELLS = HT * WD, NP = (CELLS + NT - 1) / NT;
-    __shared__ float raw[3][HT][WD];
-    __shared__ float xs[3][HT][kTileX];
+    __shared__ float raw[2][3][HT][WD];
+    __shared__ float xs[2][3][HT][kTileX];
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
@@ -440,8 +445,6 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
         const int r = c / WD, q = c - r * WD;
         coff[j] = clampi(x0 - R + q, 0, nx - 1) + nx * clampi(y0 - R + r, 0, ny - 1);
     }
-    // the next plane's staged values are prefetched into registers while the current
-    // plane is filtered
     float pre[NP][3];
     auto prefetch = [&](int p) {
         const int base = nxy * clampi(p, 0, nz - 1);
@@ -454,83 +457,81 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
             }
     };
 
-    // x then y pass of the plane held in `pre`; `p1` is prefetched meanwhile
-    auto filter_plane = [&](int p1, bool more, float out[3]) {
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            const int c = tid + j * NT;
-            if (c < CELLS) {
-                const int r = c / WD, q = c - r * WD;
-                raw[0][r][q] = pre[j][0];
-                raw[1][r][q] = pre[j][1];
-                raw[2][r][q] = pre[j][2];
-            }
-        }
-        if (more) prefetch(p1);
-        __syncthreads();
-        for (int c = tid; c < HT * kTileX; c += NT) {
-            const int r = c / kTileX, q = c - r * kTileX;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                float s = wx[0] * raw[k][r][q + R];
-#pragma unroll
-                for (int m = 1; m <= R; ++m) s = __builtin_fmaf(wx[m], raw[k][r][q + R - m] + raw[k][r][q + R + m], s);
-                xs[k][r][q] = s;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            float s = wy[0] * xs[k][ty + R][tx];
-#pragma unroll
-            for (int m = 1; m <= R; ++m) s = __builtin_fmaf(wy[m], xs[k][ty + R - m][tx] + xs[k][ty + R + m][tx], s);
-            out[k] = s;
-        }
-    };
-
     float ring[3][2 * R + 1];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int m = 0; m <= 2 * R; ++m) ring[k][m] = 0.f;
-    auto push = [&](const float v3[3]) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-#pragma unroll
-            for (int m = 0; m < 2 * R; ++m) ring[k][m] = ring[k][m + 1];
-            ring[k][2 * R] = v3[k];
-        }
-    };
 
-    float v3[3];
-    prefetch(z0 - R);
-    for (int q = 0; q < 2 * R; ++q) {
-        filter_plane(z0 - R + q + 1, true, v3);
-        push(v3);
-    }
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < nx && gy < ny;
     WarpPending wp;
     int wv = -1;
-    for (int z = z0; z < z1; ++z) {
-        filter_plane(z + R + 1, z + 1 < z1, v3);
-        push(v3);
-        if (wv >= 0) warp_finish(a.warp, wp, wv);
-        wv = -1;
-        if (own) {
-            const int v = gx + nx * gy + nxy * z;
-            float s[3];
+    const int lo = z0 - R, count = (z1 - z0) + 2 * R;  // planes lo .. lo + count - 1
+    prefetch(lo);
+    for (int i = 0; i < count + 2; ++i) {
+        // (a) plane lo + i into raw[i & 1], and the next plane's prefetch
+        if (i < count) {
+            const int sb = i & 1;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const int c = tid + j * NT;
+                if (c < CELLS) {
+                    const int r = c / WD, q = c - r * WD;
+                    raw[sb][0][r][q] = pre[j][0];
+                    raw[sb][1][r][q] = pre[j][1];
+                    raw[sb][2][r][q] = pre[j][2];
+                }
+            }
+            if (i + 1 < count) prefetch(lo + i + 1);
+        }
+        // (b) x pass of plane lo + i - 1
+        if (i >= 1 && i <= count) {
+            const int sb = (i - 1) & 1;
+            for (int c = tid; c < HT * kTileX; c += NT) {
+                const int r = c / kTileX, q = c - r * kTileX;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float t = wx[0] * raw[sb][k][r][q + R];
+#pragma unroll
+                    for (int m = 1; m <= R; ++m)
+                        t = __builtin_fmaf(wx[m], raw[sb][k][r][q + R - m] + raw[sb][k][r][q + R + m], t);
+                    xs[sb][k][r][q] = t;
+                }
+            }
+        }
+        // (c) y pass of plane lo + i - 2 into the ring; once the ring holds planes
+        // z - R .. z + R, the z pass and the output of plane z = lo + i - 2 - R
+        if (i >= 2) {
+            const int sb = i & 1;  // ((i - 2) & 1)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                float t = wz[0] * ring[k][R];
+                float t = wy[0] * xs[sb][k][ty + R][tx];
 #pragma unroll
-                for (int m = 1; m <= R; ++m) t = __builtin_fmaf(wz[m], ring[k][R - m] + ring[k][R + m], t);
-                s[k] = t;
-                stg(a.out[k], v, t);
+                for (int m = 1; m <= R; ++m) t = __builtin_fmaf(wy[m], xs[sb][k][ty + R - m][tx] + xs[sb][k][ty + R + m][tx], t);
+#pragma unroll
+                for (int m = 0; m < 2 * R; ++m) ring[k][m] = ring[k][m + 1];
+                ring[k][2 * R] = t;
             }
-            warp_issue(a.warp, gx, gy, z, s[0], s[1], s[2], wp);
-            wv = v;
+            if (wv >= 0) warp_finish(a.warp, wp, wv);
+            wv = -1;
+            if (i - 2 >= 2 * R && own) {
+                const int z = lo + i - 2 - R;
+                const int v = gx + nx * gy + nxy * z;
+                float s3[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float t = wz[0] * ring[k][R];
+#pragma unroll
+                    for (int m = 1; m <= R; ++m) t = __builtin_fmaf(wz[m], ring[k][R - m] + ring[k][R + m], t);
+                    s3[k] = t;
+                    stg(a.out[k], v, t);
+                }
+                warp_issue(a.warp, gx, gy, z, s3[0], s3[1], s3[2], wp);
+                wv = v;
+            }
         }
+        __syncthreads();
     }
     if (wv >= 0) warp_finish(a.warp, wp, wv);
 }
@@ -578,7 +579,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     // LDS small so that more blocks share a CU.)
     constexpr int kLdsBase = 4 * (4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + 9 * UCELLS + TY * kTileX);
     constexpr int kLdsMax = 160 * 1024, kKrBytes = 12 * WCELLS;
-    constexpr bool kFr32 = kLdsBase + 16 * WCELLS <= kLdsMax;
+    // (the 16-row tiles run one block per compute unit; smaller tiles keep bytes so that two
+    // blocks fit in its 160 KiB)
+    constexpr bool kFr32 = TY == 16 && kLdsBase + 16 * WCELLS <= kLdsMax;
     constexpr bool kStageK = kMasked && TY == 16 && kLdsBase + 16 * WCELLS + kKrBytes <= kLdsMax;
     using FrT = typename std::conditional<kFr32, uint32_t, uint8_t>::type;
     // One LDS buffer laid out by hand, in order of access density: the arrays read at many

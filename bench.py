@@ -223,6 +223,11 @@ def roofline(stats, pair, metric, workload, copy_gbs):
     out["bound_evidence"] = ("VALU issue %s of its ceiling, HBM traffic %s of the copy-measured rate"
                              % ("%.2f" % out["valu"]["frac"] if sq else "unmeasured",
                                 "%.2f" % busy_hbm if busy_hbm is not None else "unmeasured"))
+    if sq and "step_wait_any_over_wave_cycles" in sq:
+        # neither near its ceiling: the waves wait (memory and LDS latency, barriers)
+        out["wave_cycles_waiting"] = {name: round(sq[name + "_wait_any_over_wave_cycles"], 3) for name in per}
+        out["bound_evidence"] += ("; waves waiting %.2f (step) and %.2f (smooth) of their cycles"
+                                  % (out["wave_cycles_waiting"]["step"], out["wave_cycles_waiting"]["smooth"]))
     out["kernels"] = per
     return out
 

@@ -135,9 +135,9 @@ typedef struct cgdir_params {
                                         that unit (converted to voxels for the field),
                                         sigma_fluid and sigma_diff are in that unit (sigma / h
                                         voxels along each axis, radius ceil(3 sigma / h) <= 6),
-                                        and level l has voxel size spacing * 2^l.  x and y
-                                        must be equal (CGDIR_E_UNIMPL otherwise).
-                                        restrict_sigma and uroi_margin stay in voxels. */
+                                        and level l has voxel size spacing * 2^l; the three
+                                        axes may differ.  restrict_sigma and uroi_margin stay
+                                        in voxels. */
 } cgdir_params;
 
 /* Stopping rule (section 2.2, delta = RMS intensity difference over the UROI, l = change of
@@ -210,9 +210,9 @@ typedef struct cgdir_request {
 } cgdir_request;
 
 /* Register n pairs of uneven sizes and structure counts together on the device
- * (blocking): every iteration phase runs once for all pairs of a group that still have work;
- * the pairs are grouped by their Gaussian radii, and the groups run on two streams of the
- * context that share the device.
+ * (blocking): every iteration phase runs once for all pairs of a Gaussian radius that still
+ * have work, one launch over all their tiles (CGDIR_BATCH_LANES=2 in the environment spreads
+ * the radius groups over two streams of the context that share the device).
  * Each pair's result equals what cgdir_register returns for it alone.  status (host,
  * n entries, may be NULL) receives each pair's code.  Returns the first failing code.
  * Errors: as cgdir_register; CGDIR_E_NOMEM when the pool cannot hold all pairs at once. */

@@ -54,17 +54,17 @@ struct StepArgs {
     int k;                    // active structures (<= kMaxStructs)
     float lam[kMaxStructs];   // lambda_i
     float far_l1;             // 1 + lambda_0 + ... + lambda_{k-1}, summed in this order
-    float far_cx, far_cz;     // 2 far_l1 gx^2 and 2 far_l1 gz^2 (gx, gz = gs[0], gs[1])
-    float gs2[2];             // gs[0]^2 and gs[1]^2
+    float far_c[3];           // 2 far_l1 gs[a]^2 per axis
+    float gs2[3];             // gs[a]^2
     uint32_t neg;             // bit i: s_i = -1 (else +1); the modified images use s_i / 2
     float c0;                 // CT-number offset
     float inv_norm;           // 1 / norm_range
-    float gs[2];              // 0.5 / voxel size in-plane (x and y) and along z (0.5 in voxel
-                              // units): central differences per unit length; the step goes
-                              // back to voxels as 2 gs
-    // fluid Gaussian in-plane and along z: w[0] centre, w[m] = weight at +-m, zero past the
-    // axis' own radius (the launch's radius is the larger of the two)
-    float wxy[kMaxRadius + 1], wz[kMaxRadius + 1];
+    float gs[3];              // 0.5 / voxel size along x, y and z (0.5 in voxel units): central
+                              // differences per unit length; the step goes back to voxels as
+                              // 2 gs
+    // fluid Gaussian along x, y and z: w[0] centre, w[m] = weight at +-m, zero past the
+    // axis' own radius (the launch's radius is the largest of the three)
+    float wx[kMaxRadius + 1], wy[kMaxRadius + 1], wz[kMaxRadius + 1];
     int tz;                   // planes per block (z chunk)
     const int *stop;          // iterations after which the pair stopped (0: running)
     int iter;                 // this launch's iteration: nothing to do once *stop <= iter
@@ -76,9 +76,8 @@ struct SmoothArgs {
     const float *in[3];
     float *out[3];
     Dims d;
-    // Gaussian in-plane and along z: w[0] centre, w[m] = weight at +-m, zero past the axis'
-    // radius
-    float wxy[kMaxRadius + 1], wz[kMaxRadius + 1];
+    // Gaussian along x, y and z: w[0] centre, w[m] = weight at +-m, zero past the axis' radius
+    float wx[kMaxRadius + 1], wy[kMaxRadius + 1], wz[kMaxRadius + 1];
     int tz;
     WarpArgs warp;            // where the warp goes
     const int *stop;          // iterations after which the pair stopped (0: running)
@@ -104,7 +103,7 @@ struct DeltaJob {
 // Batched launches: one launch over the tiles of n pairs.  The descriptors travel in the
 // kernel-argument segment (<= 4 KiB), so a launch holds a bounded number of pairs.
 // prefix[q] = first block of pair q, prefix[n] = total blocks.
-constexpr int kBatchStep = 14, kBatchSmooth = 18, kBatchDelta = 64;
+constexpr int kBatchStep = 12, kBatchSmooth = 16, kBatchDelta = 64;
 struct StepBatch {
     int n;
     int prefix[kBatchStep + 1];

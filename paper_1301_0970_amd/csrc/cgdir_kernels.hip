@@ -258,7 +258,7 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
     const float ex = w[2] - w[1], ey = w[4] - w[3], ez = w[6] - w[5];
     const float d = t0 - w[0];
     *dout = d;
-    const float a02 = __builtin_fmaf(a.gs2[1], ez * ez, a.gs2[0] * __builtin_fmaf(ey, ey, ex * ex));
+    const float a02 = __builtin_fmaf(a.gs2[2], ez * ez, __builtin_fmaf(a.gs2[1], ey * ey, a.gs2[0] * (ex * ex)));
     du[0] = du[1] = du[2] = 0.f;
     // n = grad I0~ / |grad I0~| undefined at 0: no step (also below the smallest normal
     // float, where the step is below 1e-19 voxel; NaN goes on and is reported)
@@ -271,12 +271,12 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
         // never formed.  In voxels along each axis the step is that times 2 gs, i.e. 2 gs^2 L d
         // e / (L a0^2 + d^2) for the difference e (beta = d^2, Thirion).
         const float q = d * __builtin_amdgcn_rcpf(__builtin_fmaf(a.far_l1, a02, d * d));  // ~1 ulp
-        du[0] = (a.far_cx * q) * ex;
-        du[1] = (a.far_cx * q) * ey;
-        du[2] = (a.far_cz * q) * ez;
+        du[0] = (a.far_c[0] * q) * ex;
+        du[1] = (a.far_c[1] * q) * ey;
+        du[2] = (a.far_c[2] * q) * ez;
         return;
     }
-    const float g0x = a.gs[0] * ex, g0y = a.gs[0] * ey, g0z = a.gs[1] * ez;
+    const float g0x = a.gs[0] * ex, g0y = a.gs[1] * ey, g0z = a.gs[2] * ez;
     const float inv = __builtin_amdgcn_rsqf(a02);  // hardware 1/sqrt, ~1 ulp
     const float a0 = a02 * inv;
     const float nxv = g0x * inv, nyv = g0y * inv, nzv = g0z * inv;
@@ -312,8 +312,8 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
             }
             const float Kc = Kq[0];
             const float gkx = a.gs[0] * (Kq[2] - Kq[1]);
-            const float gky = a.gs[0] * (Kq[4] - Kq[3]);
-            const float gkz = a.gs[1] * (Kq[6] - Kq[5]);
+            const float gky = a.gs[1] * (Kq[4] - Kq[3]);
+            const float gkz = a.gs[2] * (Kq[6] - Kq[5]);
             const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
             const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
             const float ai = __builtin_fmaf(hs, proj, a0);
@@ -341,8 +341,8 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
                     }
                     const float Kc = Kq[0];
                     const float gkx = a.gs[0] * (Kq[1] - Kq[2]);
-                    const float gky = a.gs[0] * (Kq[3] - Kq[4]);
-                    const float gkz = a.gs[1] * (Kq[5] - Kq[6]);
+                    const float gky = a.gs[1] * (Kq[3] - Kq[4]);
+                    const float gkz = a.gs[2] * (Kq[5] - Kq[6]);
                     const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
                     const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
                     const float ai = __builtin_fmaf(hs, proj, a0);
@@ -362,8 +362,8 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
     const float vv = num * __builtin_amdgcn_rcpf(den);  // hardware reciprocal, ~1 ulp
     // v n is the step per unit length; in voxels along each axis it is v n / h = v n 2 gs
     du[0] = vv * nxv * (2.f * a.gs[0]);
-    du[1] = vv * nyv * (2.f * a.gs[0]);
-    du[2] = vv * nzv * (2.f * a.gs[1]);
+    du[1] = vv * nyv * (2.f * a.gs[1]);
+    du[2] = vv * nzv * (2.f * a.gs[2]);
 }
 
 // pair owning logical block L of a batched launch: prefix[q] <= L < prefix[q + 1]
@@ -424,14 +424,14 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
     const TileCoord tc = tile_of(TY, a.tz, a.d, L);
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
-    // in-plane (x and y share one voxel size) and z Gaussians
-    float wx[R + 1], wz[R + 1];
+    // the Gaussians along x, y and z
+    float wx[R + 1], wy[R + 1], wz[R + 1];
 #pragma unroll
     for (int m = 0; m <= R; ++m) {
-        wx[m] = a.wxy[m];
+        wx[m] = a.wx[m];
+        wy[m] = a.wy[m];
         wz[m] = a.wz[m];
     }
-    const float *wy = wx;
 
     const float *__restrict__ in0 = a.in[0];
     const float *__restrict__ in1 = a.in[1];
@@ -614,14 +614,14 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
     const bool masked = kMasked && a.F != nullptr;
     const bool metric = a.partials != nullptr;
-    // in-plane (x and y share one voxel size) and z Gaussians
-    float wx[R + 1], wz[R + 1];
+    // the Gaussians along x, y and z
+    float wx[R + 1], wy[R + 1], wz[R + 1];
 #pragma unroll
     for (int m = 0; m <= R; ++m) {
-        wx[m] = a.wxy[m];
+        wx[m] = a.wx[m];
+        wy[m] = a.wy[m];
         wz[m] = a.wz[m];
     }
-    const float *wy = wx;
 
     // ---- I0~ / structure-bit ring (tile + R + 1 halo), clamped in-plane offsets
     int woff[NW];

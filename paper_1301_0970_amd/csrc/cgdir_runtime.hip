@@ -1,6 +1,6 @@
 // Host runtime of libcgdir: pool sub-allocator, registration driver (Algorithm A:
 // pyramid, coarse demons, finest-level CG-DIR loop, stopping rule), batched execution,
-// the serving scheduler, and the C-ABI of include/cgdir.h.
+// the device side of the serving loop (cgdir_serve.h), and the C-ABI of include/cgdir.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +23,7 @@
 
 #include "cgdir.h"
 #include "cgdir_internal.h"
+#include "cgdir_serve.h"
 
 // Device memory of cgdir_register_static: every per-registration buffer of a registration that
 // may not allocate.  Each device the library runs on holds its own copy until the process ends;
@@ -49,13 +50,6 @@ void *scratch_address(int device)
         else (void)hipGetLastError();
     }
     return g_scratch[device];
-}
-
-int64_t now_ns()
-{
-    return std::chrono::duration_cast<std::chrono::nanoseconds>(
-               std::chrono::steady_clock::now().time_since_epoch())
-        .count();
 }
 
 constexpr size_t kAlign = 256;
@@ -426,20 +420,14 @@ struct cgdir_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // Lanes: streams of batched and served work, created with the context.  A batch runs its
-    // pairs in up to two lockstep groups on the two whole-device streams; the serving loop runs
-    // its requests on the whole device, or, while large and small requests are admitted
-    // together, the large ones on lane_major and the small ones on lane_minor, two streams
-    // restricted to complementary sets of compute units (minor_cus of them for the small ones).
+    // Lanes: two whole-device streams of batched and served work, created with the context.
+    // The serving loop puts its large and small requests on separate lanes (cgdir_serve.h); a
+    // batch runs its pairs in one lockstep group on lane 0, or with CGDIR_BATCH_LANES=2 its
+    // radius groups spread over both lanes (on average no faster, and less repeatable: the
+    // autotuner then times launches that share the device with the other lane's).
     hipStream_t lane_full[2] = {nullptr, nullptr};
-    hipStream_t lane_major = nullptr, lane_minor = nullptr;
-    int minor_cus = 0;          // 0: no partitioning (the masked streams are absent)
-    int batch_lanes = 2;
-    int serve_policy = 3;       // lanes of the serving loop: 0 one lockstep group on the whole
-                                // device; 1 large and small requests on the CU partition; 2 large
-                                // and small requests on the two whole-device streams; 3 as 2, with
-                                // the large requests one at a time, oldest first, unless requests
-                                // are waiting for admission
+    int batch_lanes = 1;
+    int serve_policy = kServeLanesSerial;
     int64_t large_voxels = int64_t(8) << 20;   // finest-level voxels of a large request
     void *scratch = nullptr;    // this device's static scratch (cgdir_register_static), or null
     PinRec *static_pin = nullptr;  // pinned record of cgdir_register_static
@@ -464,19 +452,9 @@ struct cgdir_ctx {
     double total_ms[K_COUNT * 8] = {};
     double voxels[K_COUNT * 8] = {};
 
-    // serving
-    std::mutex mu;
-    std::condition_variable cv;
-    std::thread sched;
-    bool sched_started = false;
-    bool stopping = false;
-    uint64_t next_ticket = 1;
-    std::deque<uint64_t> queue;
-    struct Request;
-    // records of queued, running and the CGDIR_KEEP_FINISHED latest finished requests
-    // (shared: a waiter keeps its record alive while it sleeps)
-    std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
-    std::deque<uint64_t> finished_order;
+    // serving (created with the context; its thread starts at the first submission)
+    struct Serving;
+    std::unique_ptr<Serving> serving;
     std::mutex launch_mu;  // keeps each job's launch sequence contiguous on the stream
 
     // pinned records, allocated in chunks and recycled
@@ -591,7 +569,6 @@ int check_params(const cgdir_params &p, int k)
     if (!voxel_units) {
         for (int a = 0; a < 3; ++a)
             if (!(p.spacing[a] > 0.f) || !std::isfinite(p.spacing[a])) return CGDIR_E_INVAL;
-        if (p.spacing[0] != p.spacing[1]) return CGDIR_E_UNIMPL;  // in-plane voxels are square
     }
     const float sig[3] = {p.sigma_fluid, p.sigma_diff, p.restrict_sigma};
     for (int q = 0; q < 3; ++q) {
@@ -1037,15 +1014,15 @@ struct Job {
         sa.c0 = req.params.intensity_offset;
         sa.inv_norm = 1.0f / req.params.norm_range;
         for (int m = 0; m <= kMaxRadius; ++m) {
-            sa.wxy[m] = wf[level][0][m];
+            sa.wx[m] = wf[level][0][m];
+            sa.wy[m] = wf[level][1][m];
             sa.wz[m] = wf[level][2][m];
         }
-        sa.gs[0] = gs[level][0];
-        sa.gs[1] = gs[level][2];
-        sa.gs2[0] = sa.gs[0] * sa.gs[0];
-        sa.gs2[1] = sa.gs[1] * sa.gs[1];
-        sa.far_cx = 2.f * sa.gs2[0] * sa.far_l1;
-        sa.far_cz = 2.f * sa.gs2[1] * sa.far_l1;
+        for (int a = 0; a < 3; ++a) {
+            sa.gs[a] = gs[level][a];
+            sa.gs2[a] = sa.gs[a] * sa.gs[a];
+            sa.far_c[a] = 2.f * sa.gs2[a] * sa.far_l1;
+        }
         sa.tz = ctx->tune.step_tz;
         sa.stop = delta_on ? stop_dev : nullptr;
         sa.iter = iter;
@@ -1077,7 +1054,8 @@ struct Job {
         sb.d = level_dims(d0, level);
         sb.tz = ctx->tune.smooth_tz;
         for (int m = 0; m <= kMaxRadius; ++m) {
-            sb.wxy[m] = wd[level][0][m];
+            sb.wx[m] = wd[level][0][m];
+            sb.wy[m] = wd[level][1][m];
             sb.wz[m] = wd[level][2][m];
         }
         sb.warp = warp_args();
@@ -1363,64 +1341,31 @@ int drive_lanes(cgdir_ctx *c, std::vector<LaneWork> &lanes)
 }  // namespace
 }  // namespace cgdir
 
-// ------------------------------------------------------------------ serving state
+// ------------------------------------------------------------------ serving
 
-struct cgdir_ctx::Request {
-    uint64_t ticket = 0;
-    Job job;
-    int state = CGDIR_QUEUED;
-    int error = CGDIR_OK;
-    int64_t t_submit = 0, t_admit = 0, t_done = 0;
-    int level = 0, iter = 0;   // progress mirrored for cgdir_poll (under ctx->mu)
-    double last_delta = 0.0;
-    hipEvent_t done_ev = nullptr;
-    hipEvent_t ready_ev = nullptr;  // recorded on the context stream at submission: the inputs
-                                    // the caller ordered before it are complete past it
-    bool emitted = false;
-    ~Request()
-    {
-        if (ready_ev) (void)hipEventDestroy(ready_ev);
-    }
-};
-
+// The device work of the serving loop (cgdir_serve.h): lane l is the context's stream
+// lane_full[l].  Events used here belong to the serving thread alone.
 namespace cgdir {
 namespace {
 
-// Final state of a request (under ctx->mu); the oldest finished records beyond
-// CGDIR_KEEP_FINISHED are dropped.
-void finish_request(cgdir_ctx *c, cgdir_ctx::Request *r, int code)
-{
-    r->job.release();
-    r->error = code;
-    r->state = code == CGDIR_OK ? CGDIR_DONE : (code == CGDIR_E_CANCELLED ? CGDIR_CANCELLED : CGDIR_FAILED);
-    r->t_done = now_ns();
-    c->finished_order.push_back(r->ticket);
-    while (c->finished_order.size() > (size_t)CGDIR_KEEP_FINISHED) {
-        c->reqs.erase(c->finished_order.front());
-        c->finished_order.pop_front();
-    }
-}
-
-// The serving loop.  Admission is FIFO by pool footprint and free slots.  Admitted requests
-// advance in lockstep ticks (one iteration each per tick, their launches merged), grouped into
-// lanes that each have their own stream and at most two ticks queued.  With the default policy
-// (3) the large requests (finest level of at least large_voxels) tick on one whole-device
-// stream and the small ones on the other, so that a small request does not advance at the pace
-// of a large one's launches (a small request's launches are latency-bound and share the device
-// well); while no request waits for admission the large ones run one at a time, oldest first
-// (as a serial queue would run them), and while requests wait every admitted request advances
-// (the merged launches give more registrations per second).  Policy 0 runs every request in one
-// lockstep group, 1 puts the two groups on streams restricted to complementary sets of compute
-// units, 2 is 3 without the one-at-a-time rule (CGDIR_SERVE_POLICY).  The grouping is decided
-// again whenever a request joins or leaves; a request that changes lanes has its next launches
-// ordered after its earlier ones by an event.  A request that finishes is copied out and its
-// slot and memory are recycled once its completion event has fired.  Events used here belong to
-// this thread alone.
-void scheduler(cgdir_ctx *c)
-{
-    const bool device_ok = hipSetDevice(c->device) == hipSuccess;  // (else every request fails)
+struct DeviceExec {
+    struct Work {
+        Job job;
+        hipEvent_t ready_ev = nullptr;  // recorded on the context stream at submission: the inputs
+                                        // the caller ordered before it are complete past it
+        hipEvent_t done_ev = nullptr;   // after the request's last copy (none: its stream is synced)
+        ~Work()
+        {
+            if (ready_ev) (void)hipEventDestroy(ready_ev);
+        }
+    };
+    cgdir_ctx *c;
+    std::deque<hipEvent_t> inflight[kServeLaneCount];  // end of each tick in flight
     std::vector<hipEvent_t> spare;
-    auto get_ev = [&]() -> hipEvent_t {
+
+    explicit DeviceExec(cgdir_ctx *ctx) : c(ctx) {}
+    hipEvent_t event()
+    {
         if (!spare.empty()) {
             hipEvent_t e = spare.back();
             spare.pop_back();
@@ -1429,199 +1374,107 @@ void scheduler(cgdir_ctx *c)
         hipEvent_t e = nullptr;
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
         return e;
-    };
-    struct Lane {
-        hipStream_t s;
-        std::deque<hipEvent_t> inflight;
-    };
-    const int policy = c->serve_policy == 1 && !(c->minor_cus > 0 && c->lane_major && c->lane_minor) ? 3 : c->serve_policy;
-    Lane lanes[3] = {{c->lane_full[0], {}}, {policy == 1 ? c->lane_major : c->lane_full[1], {}},
-                     {policy == 1 ? c->lane_minor : nullptr, {}}};
-    const bool can_split = policy != 0;
-    auto large = [&](const cgdir_ctx::Request *r) { return r->job.d0.n() >= c->large_voxels; };
-    std::vector<cgdir_ctx::Request *> active;
-    // lane of each admitted request under the current mix: 0 whole device, 1 major, 2 minor
-    auto lane_of = [&](const cgdir_ctx::Request *r, bool split) {
-        if (!split) return 0;
-        return policy == 1 ? (large(r) ? 1 : 2) : (large(r) ? 0 : 1);  // (2 and 3)
-    };
-    auto mixed = [&]() {
-        bool any_large = false, any_small = false;
-        for (cgdir_ctx::Request *r : active)
-            if (!r->job.finished && r->error == CGDIR_OK) (large(r) ? any_large : any_small) = true;
-        return can_split && any_large && any_small;
-    };
-    // move a request's device work to stream `to`: its next launches follow its earlier ones
-    auto move_to = [&](cgdir_ctx::Request *r, hipStream_t to) {
-        if (r->job.st == to) return;
-        hipEvent_t e = get_ev();
-        bool ok = e && hipEventRecord(e, r->job.st) == hipSuccess && hipStreamWaitEvent(to, e, 0) == hipSuccess;
-        if (!ok) (void)hipStreamSynchronize(r->job.st);  // (ordered the slow way)
-        if (e) spare.push_back(e);  // (a wait captures the event's state when it is called)
-        r->job.st = to;
-    };
-    for (;;) {
-        // admission, in arrival order.  The request leaves the queue under mu; its set-up
-        // launches run after mu is released, so that poll, submit and cancel never wait for
-        // the launch lock (a blocking registration may hold it for a long time).
-        bool changed = false;
-        for (;;) {
-            cgdir_ctx::Request *r = nullptr;
-            {
-                std::lock_guard<std::mutex> lk(c->mu);
-                while (!c->queue.empty()) {
-                    auto it = c->reqs.find(c->queue.front());
-                    if (it != c->reqs.end() && it->second->state == CGDIR_QUEUED) break;
-                    c->queue.pop_front();
-                }
-                if (c->queue.empty() || (int)active.size() >= c->max_slots) break;
-                r = c->reqs.find(c->queue.front())->second.get();
-                const int rc = device_ok ? r->job.allocate() : CGDIR_E_HIP;
-                if (rc == CGDIR_E_NOMEM) break;  // the head of the queue waits for memory
-                c->queue.pop_front();
-                if (rc != CGDIR_OK) {
-                    finish_request(c, r, rc);
-                    c->cv.notify_all();
-                    continue;
-                }
-                r->state = CGDIR_RUNNING;
-                r->t_admit = now_ns();
-            }
-            active.push_back(r);
-            // its set-up runs on the lane it joins, after the caller's inputs
-            r->job.st = lanes[lane_of(r, mixed())].s;
-            int rc = CGDIR_OK;
-            if (r->ready_ev && hipStreamWaitEvent(r->job.st, r->ready_ev, 0) != hipSuccess) rc = CGDIR_E_HIP;
-            if (rc == CGDIR_OK) {
-                std::lock_guard<std::mutex> lg(c->launch_mu);
-                rc = r->job.setup();
-            }
-            if (rc != CGDIR_OK) {
-                (void)hipStreamSynchronize(r->job.st);  // set-up work in flight may still use its memory
-                active.pop_back();
-                std::lock_guard<std::mutex> lk(c->mu);
-                finish_request(c, r, rc);
-                c->cv.notify_all();
-                continue;
-            }
-            changed = true;
-        }
-        if (active.empty()) {
-            std::unique_lock<std::mutex> lk(c->mu);
-            if (c->stopping && c->queue.empty()) break;
-            c->cv.wait_for(lk, std::chrono::milliseconds(20));  // new work, or memory for the head
-            continue;
-        }
-        bool backlog;  // requests wait for admission: throughput before the order of arrival
-        {
-            std::lock_guard<std::mutex> lk(c->mu);
-            backlog = !c->queue.empty();
-        }
-        // the large request that runs while there is no backlog (policy 3): the oldest
-        const cgdir_ctx::Request *lead = nullptr;
-        if (policy == 3 && !backlog)
-            for (cgdir_ctx::Request *r : active)
-                if (!r->job.finished && r->error == CGDIR_OK && large(r)) {
-                    lead = r;
-                    break;
-                }
-        if (changed) {  // regroup: every running request onto its lane under the new mix
-            const bool split = mixed();
-            for (cgdir_ctx::Request *r : active)
-                if (!r->job.finished && r->error == CGDIR_OK) move_to(r, lanes[lane_of(r, split)].s);
-        }
-        // one tick on every lane that has running requests and fewer than two ticks queued
-        bool issued = false, ended = false;
-        {
-            std::lock_guard<std::mutex> lg(c->launch_mu);
-            for (Lane &L : lanes) {
-                while (!L.inflight.empty() && hipEventQuery(L.inflight.front()) != hipErrorNotReady) {
-                    spare.push_back(L.inflight.front());  // (a device error shows in the completion checks)
-                    L.inflight.pop_front();
-                }
-                if (!L.s || L.inflight.size() >= 2) continue;
-                std::vector<Job *> tj;
-                std::vector<cgdir_ctx::Request *> tr;
-                for (cgdir_ctx::Request *r : active)
-                    if (!r->job.finished && r->error == CGDIR_OK && r->job.st == L.s &&
-                        !(lead && large(r) && r != lead)) {  // (later large ones wait their turn)
-                        tj.push_back(&r->job);
-                        tr.push_back(r);
-                    }
-                if (tj.empty()) continue;
-                std::vector<int> codes(tj.size(), CGDIR_OK);
-                const int rc = run_tick(c, L.s, tj, codes);
-                for (size_t i = 0; i < tj.size(); ++i) {
-                    const int code = rc != CGDIR_OK ? rc : codes[i];
-                    if (code != CGDIR_OK) {
-                        tr[i]->job.finished = true;
-                        tr[i]->error = code;
-                    }
-                }
-                hipEvent_t te = get_ev();
-                if (te) {
-                    if (hipEventRecord(te, L.s) == hipSuccess) L.inflight.push_back(te);
-                    else spare.push_back(te);
-                }
-                issued = true;
-            }
-            for (cgdir_ctx::Request *r : active) {
-                if (r->job.finished && !r->emitted) {
-                    if (r->error == CGDIR_OK) r->error = r->job.emit();
-                    r->done_ev = get_ev();
-                    if (r->done_ev && hipEventRecord(r->done_ev, r->job.st) != hipSuccess) {
-                        spare.push_back(r->done_ev);  // (completion then found by a stream sync)
-                        r->done_ev = nullptr;
-                    }
-                    r->emitted = true;
-                    ended = true;
-                }
-            }
-        }
-        // progress and completions
-        {
-            std::lock_guard<std::mutex> lk(c->mu);
-            for (size_t i = 0; i < active.size();) {
-                cgdir_ctx::Request *r = active[i];
-                r->level = r->job.level;
-                r->iter = r->job.iter;
-                r->last_delta = r->job.last_delta;
-                const hipError_t q = r->emitted && r->done_ev ? hipEventQuery(r->done_ev) : hipSuccess;
-                if (r->emitted && q != hipErrorNotReady) {
-                    // no event: wait for its copies; a failed query or sync (a device error) fails
-                    // the request instead of leaving it pending
-                    hipError_t e = q;
-                    if (!r->done_ev) e = hipStreamSynchronize(r->job.st);
-                    if (e != hipSuccess && r->error == CGDIR_OK) r->error = CGDIR_E_HIP;
-                    const int rc = r->error != CGDIR_OK ? r->error : r->job.conclude();
-                    if (r->done_ev) spare.push_back(r->done_ev);
-                    r->done_ev = nullptr;
-                    finish_request(c, r, rc);
-                    active.erase(active.begin() + i);
-                    c->cv.notify_all();
-                    ended = true;
-                } else {
-                    ++i;
-                }
-            }
-        }
-        if (ended) {  // a request left: regroup the rest
-            const bool split = mixed();
-            for (cgdir_ctx::Request *r : active)
-                if (!r->job.finished && r->error == CGDIR_OK) move_to(r, lanes[lane_of(r, split)].s);
-        }
-        if (!issued && !ended) std::this_thread::yield();
     }
-    for (Lane &L : lanes)
-        for (hipEvent_t e : L.inflight) {
-            (void)hipEventSynchronize(e);
-            spare.push_back(e);
+    bool start() { return hipSetDevice(c->device) == hipSuccess; }
+    int allocate(Work &w) { return w.job.allocate(); }
+    void release(Work &w) { w.job.release(); }
+    int setup(Work &w, int lane)
+    {
+        w.job.st = c->lane_full[lane];
+        if (w.ready_ev && hipStreamWaitEvent(w.job.st, w.ready_ev, 0) != hipSuccess) return CGDIR_E_HIP;
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        return w.job.setup();
+    }
+    void abandon(Work &w) { (void)hipStreamSynchronize(w.job.st); }
+    void move(Work &w, int lane)
+    {
+        hipStream_t to = c->lane_full[lane];
+        if (w.job.st == to) return;
+        hipEvent_t e = event();
+        const bool ok = e && hipEventRecord(e, w.job.st) == hipSuccess && hipStreamWaitEvent(to, e, 0) == hipSuccess;
+        if (!ok) (void)hipStreamSynchronize(w.job.st);  // (ordered the slow way)
+        if (e) spare.push_back(e);  // (a wait captures the event's state when it is called)
+        w.job.st = to;
+    }
+    bool lane_open(int lane)
+    {
+        std::deque<hipEvent_t> &q = inflight[lane];
+        while (!q.empty() && hipEventQuery(q.front()) != hipErrorNotReady) {
+            spare.push_back(q.front());  // (a device error shows in the completion checks)
+            q.pop_front();
         }
-    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
-}
+        return c->lane_full[lane] && q.size() < 2;
+    }
+    int tick(int lane, const std::vector<Work *> &ws, std::vector<int> &codes)
+    {
+        std::vector<Job *> jobs;
+        for (Work *w : ws) jobs.push_back(&w->job);
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        const int rc = run_tick(c, c->lane_full[lane], jobs, codes);
+        hipEvent_t te = event();
+        if (te) {
+            if (hipEventRecord(te, c->lane_full[lane]) == hipSuccess) inflight[lane].push_back(te);
+            else spare.push_back(te);
+        }
+        return rc;
+    }
+    bool finished(const Work &w) const { return w.job.finished; }
+    int64_t voxels(const Work &w) const { return w.job.d0.n(); }
+    void progress(const Work &w, int *level, int *iter, double *last_delta) const
+    {
+        *level = w.job.level;
+        *iter = w.job.iter;
+        *last_delta = w.job.last_delta;
+    }
+    int emit(Work &w, int error)
+    {
+        std::lock_guard<std::mutex> lg(c->launch_mu);
+        if (error == CGDIR_OK) error = w.job.emit();
+        w.done_ev = event();
+        if (w.done_ev && hipEventRecord(w.done_ev, w.job.st) != hipSuccess) {
+            spare.push_back(w.done_ev);  // (completion then found by a stream sync)
+            w.done_ev = nullptr;
+        }
+        return error;
+    }
+    bool done(Work &w, int error, int *code)
+    {
+        const hipError_t q = w.done_ev ? hipEventQuery(w.done_ev) : hipSuccess;
+        if (q == hipErrorNotReady) return false;
+        // no event: wait for its copies; a failed query or sync (a device error) fails the
+        // request instead of leaving it pending
+        hipError_t e = q;
+        if (!w.done_ev) e = hipStreamSynchronize(w.job.st);
+        if (e != hipSuccess && error == CGDIR_OK) error = CGDIR_E_HIP;
+        *code = error != CGDIR_OK ? error : w.job.conclude();
+        if (w.done_ev) spare.push_back(w.done_ev);
+        w.done_ev = nullptr;
+        return true;
+    }
+    void stop()
+    {
+        for (std::deque<hipEvent_t> &q : inflight)
+            for (hipEvent_t e : q) {
+                (void)hipEventSynchronize(e);
+                spare.push_back(e);
+            }
+        for (std::deque<hipEvent_t> &q : inflight) q.clear();
+        for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+        spare.clear();
+    }
+};
 
 }  // namespace
 }  // namespace cgdir
+
+struct cgdir_ctx::Serving {
+    cgdir::DeviceExec exec;
+    cgdir::Server<cgdir::DeviceExec> server;
+    explicit Serving(cgdir_ctx *c)
+        : exec(c), server(exec, c->max_slots, c->serve_policy, c->large_voxels, CGDIR_KEEP_FINISHED)
+    {
+    }
+};
 
 // ====================================================================== C-ABI
 
@@ -1711,8 +1564,6 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
     auto drop_streams = [&]() {
         for (hipStream_t &ls : c->lane_full)
             if (ls) (void)hipStreamDestroy(ls);
-        if (c->lane_major) (void)hipStreamDestroy(c->lane_major);
-        if (c->lane_minor) (void)hipStreamDestroy(c->lane_minor);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     };
     for (hipStream_t &ls : c->lane_full)
@@ -1723,27 +1574,7 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
         }
     if (const char *e = std::getenv("CGDIR_BATCH_LANES")) c->batch_lanes = std::max(1, std::min(2, std::atoi(e)));
     if (const char *e = std::getenv("CGDIR_SERVE_LARGE")) c->large_voxels = std::max<int64_t>(1, std::atoll(e));
-    if (const char *e = std::getenv("CGDIR_SERVE_POLICY")) c->serve_policy = std::max(0, std::min(3, std::atoi(e)));
-    {
-        // the CU partition of the serving loop: the last minor CUs for small requests
-        int ncu = 0;
-        int minor = 32;
-        if (const char *e = std::getenv("CGDIR_SERVE_SPLIT")) minor = std::atoi(e);
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, desc->device) == hipSuccess &&
-            minor > 0 && minor < ncu && ncu <= 32 * 16) {
-            uint32_t maj[16] = {}, mnr[16] = {};
-            const int words = (ncu + 31) / 32;
-            for (int cu = 0; cu < ncu; ++cu) (cu < ncu - minor ? maj : mnr)[cu / 32] |= 1u << (cu % 32);
-            if (hipExtStreamCreateWithCUMask(&c->lane_major, words, maj) == hipSuccess &&
-                hipExtStreamCreateWithCUMask(&c->lane_minor, words, mnr) == hipSuccess) {
-                c->minor_cus = minor;
-            } else {  // (no partitioning: every served request runs on the whole device)
-                if (c->lane_major) (void)hipStreamDestroy(c->lane_major);
-                c->lane_major = c->lane_minor = nullptr;
-                (void)hipGetLastError();
-            }
-        }
-    }
+    if (const char *e = std::getenv("CGDIR_SERVE_POLICY")) c->serve_policy = std::max(0, std::min(2, std::atoi(e)));
     void *pool = desc->pool;
     if (!pool) {
         if (hipMalloc(&c->own_pool, desc->pool_bytes) != hipSuccess) {
@@ -1756,6 +1587,7 @@ int cgdir_create(cgdir_ctx **out, const cgdir_ctx_desc *desc)
     // set-up of cgdir_register_static (nothing is allocated in that call itself)
     c->scratch = scratch_address(desc->device);
     c->static_pin = c->take_pin();
+    c->serving.reset(new cgdir_ctx::Serving(c.get()));
     *out = c.release();
     return CGDIR_OK;
 }
@@ -1764,20 +1596,9 @@ int cgdir_destroy(cgdir_ctx *c)
 {
     if (!c) return CGDIR_E_INVAL;
     (void)hipSetDevice(c->device);  // (tear-down goes on whatever the device's state)
-    {
-        std::lock_guard<std::mutex> lk(c->mu);
-        for (uint64_t t : c->queue) {
-            auto it = c->reqs.find(t);
-            if (it != c->reqs.end() && it->second->state == CGDIR_QUEUED)
-                finish_request(c, it->second.get(), CGDIR_E_CANCELLED);
-        }
-        c->queue.clear();
-        c->stopping = true;
-    }
-    c->cv.notify_all();
-    if (c->sched_started) c->sched.join();
+    if (c->serving) c->serving->server.stop();  // queued requests cancelled, admitted ones finished
     (void)hipStreamSynchronize(c->stream);
-    for (hipStream_t ls : {c->lane_full[0], c->lane_full[1], c->lane_major, c->lane_minor})
+    for (hipStream_t ls : c->lane_full)
         if (ls) (void)hipStreamSynchronize(ls);
     {
         std::lock_guard<std::mutex> g(c->prof_mu);
@@ -1791,7 +1612,8 @@ int cgdir_destroy(cgdir_ctx *c)
     }
     for (PinRec *chunk : c->pin_chunks) (void)hipHostFree(chunk);
     if (c->own_pool) (void)hipFree(c->own_pool);
-    for (hipStream_t ls : {c->lane_full[0], c->lane_full[1], c->lane_major, c->lane_minor})
+    c->serving.reset();
+    for (hipStream_t ls : c->lane_full)
         if (ls) {
             (void)hipStreamSynchronize(ls);
             (void)hipStreamDestroy(ls);
@@ -2251,75 +2073,34 @@ int cgdir_evaluate(cgdir_ctx *c, const cgdir_volume *target, const cgdir_volume 
 int cgdir_submit(cgdir_ctx *c, const cgdir_request *req, uint64_t *ticket)
 {
     if (!c || !req || !ticket) return CGDIR_E_INVAL;
-    std::shared_ptr<cgdir_ctx::Request> r = std::make_shared<cgdir_ctx::Request>();
-    CG_TRY(r->job.init(c, *req));
-    if (r->job.need() > c->pool.size()) return CGDIR_E_NOMEM;
-    r->t_submit = now_ns();
-    // the scheduler runs the request on its lane streams after this point of the context stream
+    using Req = Server<DeviceExec>::Request;
+    std::shared_ptr<Req> r = std::make_shared<Req>();
+    CG_TRY(r->work.job.init(c, *req));
+    if (r->work.job.need() > c->pool.size()) return CGDIR_E_NOMEM;
+    // the serving loop runs the request on its lane streams after this point of the context stream
     if (hipSetDevice(c->device) != hipSuccess ||
-        hipEventCreateWithFlags(&r->ready_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(r->ready_ev, c->stream) != hipSuccess)
+        hipEventCreateWithFlags(&r->work.ready_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(r->work.ready_ev, c->stream) != hipSuccess)
         return CGDIR_E_HIP;
-    std::lock_guard<std::mutex> lk(c->mu);
-    if (c->stopping) return CGDIR_E_INVAL;
-    const uint64_t t = c->next_ticket++;
-    r->ticket = t;
-    c->reqs[t] = std::move(r);
-    c->queue.push_back(t);
-    *ticket = t;
-    if (!c->sched_started) {
-        c->sched = std::thread(scheduler, c);
-        c->sched_started = true;
-    }
-    c->cv.notify_all();
-    return CGDIR_OK;
+    return c->serving->server.submit(std::move(r), ticket);
 }
 
 int cgdir_poll(cgdir_ctx *c, uint64_t ticket, cgdir_status *st)
 {
     if (!c || !st) return CGDIR_E_INVAL;
-    std::lock_guard<std::mutex> lk(c->mu);
-    auto it = c->reqs.find(ticket);
-    if (it == c->reqs.end()) return CGDIR_E_NOTFOUND;
-    const cgdir_ctx::Request &r = *it->second;
-    st->state = r.state;
-    st->error = r.error;
-    st->level = r.level;
-    st->iter = r.iter;
-    st->last_delta = r.last_delta;
-    st->t_submit_ns = r.t_submit;
-    st->t_admit_ns = r.t_admit;
-    st->t_done_ns = r.t_done;
-    return CGDIR_OK;
+    return c->serving->server.poll(ticket, st);
 }
 
 int cgdir_cancel(cgdir_ctx *c, uint64_t ticket)
 {
     if (!c) return CGDIR_E_INVAL;
-    std::lock_guard<std::mutex> lk(c->mu);
-    auto it = c->reqs.find(ticket);
-    if (it == c->reqs.end()) return CGDIR_E_NOTFOUND;
-    if (it->second->state != CGDIR_QUEUED) return CGDIR_E_BUSY;
-    finish_request(c, it->second.get(), CGDIR_E_CANCELLED);
-    c->cv.notify_all();
-    return CGDIR_OK;
+    return c->serving->server.cancel(ticket);
 }
 
 int cgdir_wait(cgdir_ctx *c, uint64_t ticket, int64_t timeout_ns)
 {
     if (!c) return CGDIR_E_INVAL;
-    std::unique_lock<std::mutex> lk(c->mu);
-    auto final_state = [&](int s) { return s == CGDIR_DONE || s == CGDIR_FAILED || s == CGDIR_CANCELLED; };
-    auto it = c->reqs.find(ticket);
-    if (it == c->reqs.end()) return CGDIR_E_NOTFOUND;
-    const std::shared_ptr<cgdir_ctx::Request> r = it->second;  // alive while this thread sleeps
-    auto pred = [&] { return final_state(r->state); };
-    if (timeout_ns < 0) {
-        c->cv.wait(lk, pred);
-    } else if (!c->cv.wait_for(lk, std::chrono::nanoseconds(timeout_ns), pred)) {
-        return CGDIR_E_TIMEOUT;
-    }
-    return r->error;
+    return c->serving->server.wait(ticket, timeout_ns);
 }
 
 int cgdir_tuning_export(cgdir_ctx *c, char *buf, size_t cap, size_t *len)

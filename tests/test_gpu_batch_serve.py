@@ -32,9 +32,13 @@ def _items(pairs):
     return [(dev(p.target), dev(p.moving), dev(p.target_masks), dev(p.moving_masks)) for p in pairs]
 
 
-def test_batch_equals_alone():
+@pytest.mark.parametrize("lanes", ["1", "2"])
+def test_batch_equals_alone(lanes, monkeypatch):
+    """Batched fields equal each pair alone, in one lockstep group and with the radius groups
+    on two streams (CGDIR_BATCH_LANES, read when the context is created)."""
     import torch
     from paper_1301_0970_amd import cgdir
+    monkeypatch.setenv("CGDIR_BATCH_LANES", lanes)
     pairs = _pairs()
     items = _items(pairs)
     prms = [cgdir.params_for_pair(p) for p in pairs]
@@ -42,7 +46,7 @@ def test_batch_equals_alone():
         say("alone")
         alone = [ctx.register(*it, prm=pr).cpu().numpy() for it, pr in zip(items, prms)]
         outs = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
-        say("batch")
+        say("batch, %s lane(s)" % lanes)
         rc, st = ctx.register_batch(items, prms, outs)
         assert rc == cgdir.OK and st == [0] * len(pairs)
         for a, o in zip(alone, outs):
@@ -134,7 +138,7 @@ def test_cancel_and_oversize():
 
 
 def test_batch_of_many_small_pairs_spans_several_launches():
-    """More pairs than one launch's descriptor table holds (14 for the step, 18 for the
+    """More pairs than one launch's descriptor table holds (12 for the step, 16 for the
     smoothing): chunked launches, results still equal to each pair alone."""
     import torch
     from paper_1301_0970_amd import cgdir

@@ -156,12 +156,15 @@ def test_step_with_different_sigmas(ctx, orc):
     assert np.abs(ug - uo).max() <= STEP_TOL
 
 
-@pytest.mark.parametrize("spacing,sigma", [((1.97, 1.97, 2.5), 1.97), ((1.2, 1.2, 3.0), 2.0)],
-                         ids=["1.97x1.97x2.5 mm sigma 1.97", "1.2x1.2x3 mm sigma 2"])
+@pytest.mark.parametrize("spacing,sigma", [((1.97, 1.97, 2.5), 1.97), ((1.2, 1.2, 3.0), 2.0),
+                                           ((0.9, 1.3, 2.5), 1.5), ((1.4, 0.8, 1.1), 1.2)],
+                         ids=["1.97x1.97x2.5 mm sigma 1.97", "1.2x1.2x3 mm sigma 2",
+                              "0.9x1.3x2.5 mm sigma 1.5", "1.4x0.8x1.1 mm sigma 1.2"])
 def test_step_in_physical_units(ctx, orc, spacing, sigma):
     """Anisotropic voxels: gradients per mm, the step in mm converted to voxels, Gaussians of
     sigma mm (in the second case radius 5 in-plane and 2 or 3 along z: the z taps are
-    zero-padded to the launch radius)."""
+    zero-padded to the launch radius; in the last two x and y differ, with radii 5, 4, 2 and
+    3, 5, 4 along x, y, z)."""
     from paper_1301_0970_amd import cgdir
     pair = P.head_neck_pair(dims=(110, 84, 40), amp=4.0, k=3)
     u0 = P.random_smooth_field(pair.dims, 3.0, 17)
@@ -195,9 +198,16 @@ def test_pyramid_in_physical_units(ctx, orc):
     rms = np.sqrt(((orc.warp(pair.moving, ug) - orc.warp(pair.moving, uo)) ** 2).mean())
     say("  final max err %.3g voxel, warped rms %.3g HU" % (err, rms))
     assert err <= FINAL_TOL and rms <= WARP_RMS_TOL
-    with pytest.raises(cgdir.CgdirError) as e:   # in-plane voxels must be square
-        gpu_register(ctx, pair, cgdir.params_for_pair(pair, spacing=(1.0, 1.5, 2.0)))
-    assert e.value.code == cgdir.E_UNIMPL
+    # x and y voxel sizes that differ
+    h2 = (1.2, 1.6, 2.0)
+    ug = gpu_register(ctx, pair, cgdir.params_for_pair(pair, sigma_fluid=2.0, sigma_diff=2.0, spacing=h2))
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, sigma_fluid=2.0, sigma_diff=2.0,
+                                           spacing=[float(np.float32(v)) for v in h2]))
+    err = np.abs(ug - uo).max()
+    rms = np.sqrt(((orc.warp(pair.moving, ug) - orc.warp(pair.moving, uo)) ** 2).mean())
+    say("  %s mm: final max err %.3g voxel, warped rms %.3g HU" % (h2, err, rms))
+    assert err <= FINAL_TOL and rms <= WARP_RMS_TOL
     for bad in ((1.0, 1.0, -2.0), (0.2, 0.2, 0.2)):   # negative; sigma 1 mm = 5 voxels -> radius 15
         with pytest.raises(cgdir.CgdirError) as e:
             gpu_register(ctx, pair, cgdir.params_for_pair(pair, spacing=bad))

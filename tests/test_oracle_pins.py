@@ -623,11 +623,11 @@ def test_anisotropic_gaussian_and_gradient(orc):
     np.testing.assert_allclose(g[2][inner], Z[inner], atol=1e-11)
 
 
-@pytest.mark.parametrize("axis", [0, 2])
-def test_force_on_a_physical_ramp(orc, axis):
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("h", [(1.97, 1.97, 2.5), (0.9, 1.3, 2.5)], ids=["square in-plane", "x != y"])
+def test_force_on_a_physical_ramp(orc, axis, h):
     """A ramp of slope a HU per unit length along one axis, target offset by c: the gradient
     is a, the demons step is c a / (a^2 + c^2) in length units, i.e. that over h voxels."""
-    h = (1.97, 1.97, 2.5)
     a, c = 40.0, 25.0
     z, y, x = _grid((9, 10, 11))
     coord = (x, y, z)[axis] * h[axis]

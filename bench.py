@@ -151,8 +151,11 @@ def copy_peak_gbs(torch, mib=1024, reps=10):
     return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
+_START = time.time()
+
+
 def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+    print("[%6.1f s] %s" % (time.time() - _START, msg), file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():

@@ -248,7 +248,8 @@ __device__ __forceinline__ void warp_finish(const WarpArgs &w, const WarpPending
 // one below, 2 the one above; rows kRow apart), read only where f[q] is nonzero; without
 // staging (kLds false) K~ is read from memory.
 // ============================================================================
-template <bool kLds, int kRow>
+// kAniso: the voxel sizes along x and y differ (else the y axis takes x's scale).
+template <bool kLds, int kRow, bool kAniso>
 __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], const uint32_t f[7], float t0,
                                          uint32_t tb, int gx, int gy, int gz, const float *lamt, const float *kl,
                                          const int ks[3], float du[3], float *dout)
@@ -258,7 +259,9 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
     const float ex = w[2] - w[1], ey = w[4] - w[3], ez = w[6] - w[5];
     const float d = t0 - w[0];
     *dout = d;
-    const float a02 = __builtin_fmaf(a.gs2[2], ez * ez, __builtin_fmaf(a.gs2[1], ey * ey, a.gs2[0] * (ex * ex)));
+    const float a02 = kAniso ? __builtin_fmaf(a.gs2[2], ez * ez, __builtin_fmaf(a.gs2[1], ey * ey, a.gs2[0] * (ex * ex)))
+                             : __builtin_fmaf(a.gs2[2], ez * ez, a.gs2[0] * __builtin_fmaf(ey, ey, ex * ex));
+    const float sy = kAniso ? a.gs[1] : a.gs[0];  // the y scale
     du[0] = du[1] = du[2] = 0.f;
     // n = grad I0~ / |grad I0~| undefined at 0: no step (also below the smallest normal
     // float, where the step is below 1e-19 voxel; NaN goes on and is reported)
@@ -272,11 +275,11 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
         // e / (L a0^2 + d^2) for the difference e (beta = d^2, Thirion).
         const float q = d * __builtin_amdgcn_rcpf(__builtin_fmaf(a.far_l1, a02, d * d));  // ~1 ulp
         du[0] = (a.far_c[0] * q) * ex;
-        du[1] = (a.far_c[1] * q) * ey;
+        du[1] = ((kAniso ? a.far_c[1] : a.far_c[0]) * q) * ey;
         du[2] = (a.far_c[2] * q) * ez;
         return;
     }
-    const float g0x = a.gs[0] * ex, g0y = a.gs[1] * ey, g0z = a.gs[2] * ez;
+    const float g0x = a.gs[0] * ex, g0y = sy * ey, g0z = a.gs[2] * ez;
     const float inv = __builtin_amdgcn_rsqf(a02);  // hardware 1/sqrt, ~1 ulp
     const float a0 = a02 * inv;
     const float nxv = g0x * inv, nyv = g0y * inv, nzv = g0z * inv;
@@ -312,7 +315,7 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
             }
             const float Kc = Kq[0];
             const float gkx = a.gs[0] * (Kq[2] - Kq[1]);
-            const float gky = a.gs[1] * (Kq[4] - Kq[3]);
+            const float gky = sy * (Kq[4] - Kq[3]);
             const float gkz = a.gs[2] * (Kq[6] - Kq[5]);
             const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
             const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
@@ -341,7 +344,7 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
                     }
                     const float Kc = Kq[0];
                     const float gkx = a.gs[0] * (Kq[1] - Kq[2]);
-                    const float gky = a.gs[1] * (Kq[3] - Kq[4]);
+                    const float gky = sy * (Kq[3] - Kq[4]);
                     const float gkz = a.gs[2] * (Kq[5] - Kq[6]);
                     const float proj = __builtin_fmaf(gkz, nzv, __builtin_fmaf(gky, nyv, gkx * nxv));
                     const float hs = ((a.neg >> i) & 1u) ? -0.5f : 0.5f;
@@ -362,7 +365,7 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
     const float vv = num * __builtin_amdgcn_rcpf(den);  // hardware reciprocal, ~1 ulp
     // v n is the step per unit length; in voxels along each axis it is v n / h = v n 2 gs
     du[0] = vv * nxv * (2.f * a.gs[0]);
-    du[1] = vv * nyv * (2.f * a.gs[1]);
+    du[1] = vv * nyv * (2.f * sy);
     du[2] = vv * nzv * (2.f * a.gs[2]);
 }
 
@@ -411,7 +414,7 @@ __global__ void __launch_bounds__(256) k_brick_occupancy(const uint8_t *__restri
 // its three stages' latencies overlap.  The warp of an output plane is issued after the plane's
 // store and finished one step later, so its gathers overlap the next step's filtering.
 // ============================================================================
-template <int R, int TY>
+template <int R, int TY, bool kAniso>
 __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
 {
     constexpr int WD = kTileX + 2 * R, HT = TY + 2 * R, NT = kTileX * TY;
@@ -424,14 +427,15 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, nxy = nx * ny;
     const TileCoord tc = tile_of(TY, a.tz, a.d, L);
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
-    // the Gaussians along x, y and z
-    float wx[R + 1], wy[R + 1], wz[R + 1];
+    // the Gaussians along x, y and z (y takes x's unless the voxel sizes differ)
+    float wx[R + 1], wyv[R + 1], wz[R + 1];
 #pragma unroll
     for (int m = 0; m <= R; ++m) {
         wx[m] = a.wx[m];
-        wy[m] = a.wy[m];
+        if constexpr (kAniso) wyv[m] = a.wy[m];
         wz[m] = a.wz[m];
     }
+    const float *wy = kAniso ? wyv : wx;
 
     const float *__restrict__ in0 = a.in[0];
     const float *__restrict__ in1 = a.in[1];
@@ -536,7 +540,7 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
     if (wv >= 0) warp_finish(a.warp, wp, wv);
 }
 
-template <int R, int TY>
+template <int R, int TY, bool kAniso>
 __global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
 {
     const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
@@ -545,7 +549,7 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
         const int s = *b.d[q].stop;
         if (s != 0 && s <= b.d[q].iter) return;
     }
-    smooth_tile<R, TY>(b.d[q], L - b.prefix[q]);
+    smooth_tile<R, TY, kAniso>(b.d[q], L - b.prefix[q]);
 }
 
 // ============================================================================
@@ -564,7 +568,7 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
 // ============================================================================
 // kMasked false: no pair of the launch has contour terms at its level (no structure bits, K~
 // or contour weights in LDS, so the block needs less of it and of registers).
-template <int R, int TY, bool kMasked>
+template <int R, int TY, bool kMasked, bool kAniso>
 __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
 {
     constexpr int WD = kTileX + 2 * R, HT = TY + 2 * R, NT = kTileX * TY;
@@ -614,14 +618,15 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
     const bool masked = kMasked && a.F != nullptr;
     const bool metric = a.partials != nullptr;
-    // the Gaussians along x, y and z
-    float wx[R + 1], wy[R + 1], wz[R + 1];
+    // the Gaussians along x, y and z (y takes x's unless the voxel sizes differ)
+    float wx[R + 1], wyv[R + 1], wz[R + 1];
 #pragma unroll
     for (int m = 0; m <= R; ++m) {
         wx[m] = a.wx[m];
-        wy[m] = a.wy[m];
+        if constexpr (kAniso) wyv[m] = a.wy[m];
         wz[m] = a.wz[m];
     }
+    const float *wy = kAniso ? wyv : wx;
 
     // ---- I0~ / structure-bit ring (tile + R + 1 halo), clamped in-plane offsets
     int woff[NW];
@@ -841,7 +846,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                         for (int q = 0; q < 7; ++q) f7[q] = 0u;
                     }
                     float du[3], d;
-                    force_at<kStageK, WW>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, &lamt[0][0],
+                    force_at<kStageK, WW, kAniso>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, &lamt[0][0],
                                           kStageK ? &Kr[0][0] + wo : nullptr, kslots, du, &d);
                     (&raw[0][0][0])[c] = du[0];  // cell c is row c / WD, column c % WD
                     (&raw[1][0][0])[c] = du[1];
@@ -950,7 +955,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     }
 }
 
-template <int R, int TY, bool kMasked>
+template <int R, int TY, bool kMasked, bool kAniso>
 __global__ void __launch_bounds__(kTileX *TY) k_step_batch(StepBatch b)
 {
     const int L = xcd_logical(blockIdx.x, b.prefix[b.n]);
@@ -959,7 +964,7 @@ __global__ void __launch_bounds__(kTileX *TY) k_step_batch(StepBatch b)
         const int s = *b.d[q].stop;
         if (s != 0 && s <= b.d[q].iter) return;
     }
-    step_tile<R, TY, kMasked>(b.d[q], L - b.prefix[q]);
+    step_tile<R, TY, kMasked, kAniso>(b.d[q], L - b.prefix[q]);
 }
 
 // Warp of the moving image with the field at the start of a level (the smoothing of u
@@ -1270,49 +1275,71 @@ static int tiles_xy(Dims d, int ty) { return ((d.nx + kTileX - 1) / kTileX) * ((
 
 int tile_blocks(Dims d, int ty, int tz) { return tiles_xy(d, ty) * ((d.nz + tz - 1) / tz); }
 
-// one launch per (radius, tile rows, contour terms in the launch) instantiation
-template <int TY, bool kMasked>
+// one launch per (radius, tile rows, contour terms in the launch, x and y voxel sizes
+// differ) instantiation
+template <int TY, bool kMasked, bool kAniso>
 static hipError_t step_batch_ty(const StepBatch &b, int radius, hipStream_t s)
 {
     const dim3 grid(b.prefix[b.n]), block(kTileX * TY);
     switch (radius) {
-    case 0: hipLaunchKernelGGL((k_step_batch<0, TY, kMasked>), grid, block, 0, s, b); break;
-    case 1: hipLaunchKernelGGL((k_step_batch<1, TY, kMasked>), grid, block, 0, s, b); break;
-    case 2: hipLaunchKernelGGL((k_step_batch<2, TY, kMasked>), grid, block, 0, s, b); break;
-    case 3: hipLaunchKernelGGL((k_step_batch<3, TY, kMasked>), grid, block, 0, s, b); break;
-    case 4: hipLaunchKernelGGL((k_step_batch<4, TY, kMasked>), grid, block, 0, s, b); break;
-    case 5: hipLaunchKernelGGL((k_step_batch<5, TY, kMasked>), grid, block, 0, s, b); break;
-    case 6: hipLaunchKernelGGL((k_step_batch<6, TY, kMasked>), grid, block, 0, s, b); break;
+    case 0: hipLaunchKernelGGL((k_step_batch<0, TY, kMasked, kAniso>), grid, block, 0, s, b); break;
+    case 1: hipLaunchKernelGGL((k_step_batch<1, TY, kMasked, kAniso>), grid, block, 0, s, b); break;
+    case 2: hipLaunchKernelGGL((k_step_batch<2, TY, kMasked, kAniso>), grid, block, 0, s, b); break;
+    case 3: hipLaunchKernelGGL((k_step_batch<3, TY, kMasked, kAniso>), grid, block, 0, s, b); break;
+    case 4: hipLaunchKernelGGL((k_step_batch<4, TY, kMasked, kAniso>), grid, block, 0, s, b); break;
+    case 5: hipLaunchKernelGGL((k_step_batch<5, TY, kMasked, kAniso>), grid, block, 0, s, b); break;
+    case 6: hipLaunchKernelGGL((k_step_batch<6, TY, kMasked, kAniso>), grid, block, 0, s, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int TY>
+static hipError_t step_batch_flags(const StepBatch &b, int radius, bool masked, bool aniso, hipStream_t s)
+{
+    if (aniso) return masked ? step_batch_ty<TY, true, true>(b, radius, s) : step_batch_ty<TY, false, true>(b, radius, s);
+    return masked ? step_batch_ty<TY, true, false>(b, radius, s) : step_batch_ty<TY, false, false>(b, radius, s);
+}
+
+// the y axis has its own scale and taps (the general instantiation) only where they differ
+// from x's: square in-plane voxels run the instantiation that reuses x's
+static bool differs(const float *a, const float *b, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (a[i] != b[i]) return true;
+    return false;
+}
+
 hipError_t launch_step_batch(const StepBatch &b, int radius, int ty, hipStream_t s)
 {
     if (b.n < 1 || b.n > kBatchStep || b.prefix[b.n] < 1) return hipErrorInvalidValue;
-    bool masked = false;  // any pair of the launch with contour terms at its level
-    for (int i = 0; i < b.n; ++i) masked = masked || b.d[i].F != nullptr;
+    bool masked = false, aniso = false;  // any pair of the launch with contour terms at its
+                                         // level; with x and y voxel sizes that differ
+    for (int i = 0; i < b.n; ++i) {
+        masked = masked || b.d[i].F != nullptr;
+        aniso = aniso || b.d[i].gs[0] != b.d[i].gs[1] || b.d[i].far_c[0] != b.d[i].far_c[1] ||
+                b.d[i].gs2[0] != b.d[i].gs2[1] || differs(b.d[i].wx, b.d[i].wy, kMaxRadius + 1);
+    }
     switch (ty) {
-    case 4: return masked ? step_batch_ty<4, true>(b, radius, s) : step_batch_ty<4, false>(b, radius, s);
-    case 8: return masked ? step_batch_ty<8, true>(b, radius, s) : step_batch_ty<8, false>(b, radius, s);
-    case 16: return masked ? step_batch_ty<16, true>(b, radius, s) : step_batch_ty<16, false>(b, radius, s);
+    case 4: return step_batch_flags<4>(b, radius, masked, aniso, s);
+    case 8: return step_batch_flags<8>(b, radius, masked, aniso, s);
+    case 16: return step_batch_flags<16>(b, radius, masked, aniso, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int TY>
+template <int TY, bool kAniso>
 static hipError_t smooth_batch_ty(const SmoothBatch &b, int radius, hipStream_t s)
 {
     const dim3 grid(b.prefix[b.n]), block(kTileX * TY);
     switch (radius) {
-    case 0: hipLaunchKernelGGL((k_smooth_batch<0, TY>), grid, block, 0, s, b); break;
-    case 1: hipLaunchKernelGGL((k_smooth_batch<1, TY>), grid, block, 0, s, b); break;
-    case 2: hipLaunchKernelGGL((k_smooth_batch<2, TY>), grid, block, 0, s, b); break;
-    case 3: hipLaunchKernelGGL((k_smooth_batch<3, TY>), grid, block, 0, s, b); break;
-    case 4: hipLaunchKernelGGL((k_smooth_batch<4, TY>), grid, block, 0, s, b); break;
-    case 5: hipLaunchKernelGGL((k_smooth_batch<5, TY>), grid, block, 0, s, b); break;
-    case 6: hipLaunchKernelGGL((k_smooth_batch<6, TY>), grid, block, 0, s, b); break;
+    case 0: hipLaunchKernelGGL((k_smooth_batch<0, TY, kAniso>), grid, block, 0, s, b); break;
+    case 1: hipLaunchKernelGGL((k_smooth_batch<1, TY, kAniso>), grid, block, 0, s, b); break;
+    case 2: hipLaunchKernelGGL((k_smooth_batch<2, TY, kAniso>), grid, block, 0, s, b); break;
+    case 3: hipLaunchKernelGGL((k_smooth_batch<3, TY, kAniso>), grid, block, 0, s, b); break;
+    case 4: hipLaunchKernelGGL((k_smooth_batch<4, TY, kAniso>), grid, block, 0, s, b); break;
+    case 5: hipLaunchKernelGGL((k_smooth_batch<5, TY, kAniso>), grid, block, 0, s, b); break;
+    case 6: hipLaunchKernelGGL((k_smooth_batch<6, TY, kAniso>), grid, block, 0, s, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1321,10 +1348,12 @@ static hipError_t smooth_batch_ty(const SmoothBatch &b, int radius, hipStream_t 
 hipError_t launch_smooth_batch(const SmoothBatch &b, int radius, int ty, hipStream_t s)
 {
     if (b.n < 1 || b.n > kBatchSmooth || b.prefix[b.n] < 1) return hipErrorInvalidValue;
+    bool aniso = false;
+    for (int i = 0; i < b.n; ++i) aniso = aniso || differs(b.d[i].wx, b.d[i].wy, kMaxRadius + 1);
     switch (ty) {
-    case 4: return smooth_batch_ty<4>(b, radius, s);
-    case 8: return smooth_batch_ty<8>(b, radius, s);
-    case 16: return smooth_batch_ty<16>(b, radius, s);
+    case 4: return aniso ? smooth_batch_ty<4, true>(b, radius, s) : smooth_batch_ty<4, false>(b, radius, s);
+    case 8: return aniso ? smooth_batch_ty<8, true>(b, radius, s) : smooth_batch_ty<8, false>(b, radius, s);
+    case 16: return aniso ? smooth_batch_ty<16, true>(b, radius, s) : smooth_batch_ty<16, false>(b, radius, s);
     default: return hipErrorInvalidValue;
     }
 }

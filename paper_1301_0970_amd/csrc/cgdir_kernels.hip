@@ -259,8 +259,11 @@ __device__ __forceinline__ void force_at(const StepArgs &a, const float w[7], co
     const float ex = w[2] - w[1], ey = w[4] - w[3], ez = w[6] - w[5];
     const float d = t0 - w[0];
     *dout = d;
-    const float a02 = kAniso ? __builtin_fmaf(a.gs2[2], ez * ez, __builtin_fmaf(a.gs2[1], ey * ey, a.gs2[0] * (ex * ex)))
-                             : __builtin_fmaf(a.gs2[2], ez * ez, a.gs2[0] * __builtin_fmaf(ey, ey, ex * ex));
+    // (a pair with square in-plane voxels takes the same arithmetic in both instantiations, so
+    // that its result does not depend on the other pairs of its launch)
+    const float a02 = kAniso && a.gs2[0] != a.gs2[1]
+                          ? __builtin_fmaf(a.gs2[2], ez * ez, __builtin_fmaf(a.gs2[1], ey * ey, a.gs2[0] * (ex * ex)))
+                          : __builtin_fmaf(a.gs2[2], ez * ez, a.gs2[0] * __builtin_fmaf(ey, ey, ex * ex));
     const float sy = kAniso ? a.gs[1] : a.gs[0];  // the y scale
     du[0] = du[1] = du[2] = 0.f;
     // n = grad I0~ / |grad I0~| undefined at 0: no step (also below the smallest normal

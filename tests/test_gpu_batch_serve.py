@@ -330,6 +330,36 @@ def test_mixed_parameters_batched_and_served_equal_alone():
             np.testing.assert_array_equal(a, o.cpu().numpy(), err_msg="served pair %d" % i)
 
 
+def test_square_and_anisotropic_in_plane_voxels_share_a_launch():
+    """A pair with square in-plane voxels batched with one whose x and y voxel sizes differ (the
+    same Gaussian radii, so their tiles share every launch, which then takes the kernels'
+    general instantiation): each field equals the pair's alone bitwise, also served."""
+    import torch
+    from paper_1301_0970_amd import cgdir
+    pairs = [P.head_neck_pair(dims=(70, 58, 30), amp=3.0, k=3, levels=2, iters=6, seed=71),
+             P.pelvis_pair(dims=(76, 64, 28), amp=3.0, k=4, levels=2, iters=6, bulge=0.0, seed=72)]
+    # sigma 2 mm: radii 5, 5, 3 (x, y, z) for the first, 5, 4, 3 for the second
+    prms = [cgdir.params_for_pair(pairs[0], spacing=(1.2, 1.2, 2.0), sigma_fluid=2.0, sigma_diff=2.0),
+            cgdir.params_for_pair(pairs[1], spacing=(1.25, 1.5, 2.0), sigma_fluid=2.0, sigma_diff=2.0)]
+    items = _items(pairs)
+    with cgdir.Context(2 << 30, max_slots=4) as ctx:
+        say("square and anisotropic: alone")
+        alone = [ctx.register(*it, prm=pr).cpu().numpy() for it, pr in zip(items, prms)]
+        outs = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
+        say("square and anisotropic: batch")
+        rc, st = ctx.register_batch(items, prms, outs)
+        assert rc == cgdir.OK and st == [cgdir.OK] * len(pairs)
+        for i, (a, o) in enumerate(zip(alone, outs)):
+            np.testing.assert_array_equal(a, o.cpu().numpy(), err_msg="batched pair %d" % i)
+        say("square and anisotropic: served")
+        outs = [torch.empty((3,) + tuple(p.target.shape), device="cuda") for p in pairs]
+        tickets = [ctx.submit(*it, pr, o) for it, pr, o in zip(items, prms, outs)]
+        for t in tickets:
+            assert ctx.wait(t, int(60e9)) == cgdir.OK
+        for i, (a, o) in enumerate(zip(alone, outs)):
+            np.testing.assert_array_equal(a, o.cpu().numpy(), err_msg="served pair %d" % i)
+
+
 def test_tuning_export_and_import():
     """A context's settled tile-shape groups export as text; a fresh context that imports them
     launches with those shapes without timing candidates (every group forced to one shape is

@@ -17,6 +17,7 @@ namespace {
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return __builtin_fmaf(t, b - a, a); }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
 // Loads and stores at an element index.  A volume holds at most 2^30 voxels, so a byte
 // offset fits in 32 bits and the address is a scalar base plus a 32-bit vector offset: no
@@ -584,8 +585,23 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     // of three staged planes (the warped masked moving image of the one structure near a
     // cell), so that the force near a structure reads no memory.  (Smaller tiles keep their
     // LDS small so that more blocks share a CU.)
-    constexpr int kLdsBase = 4 * (4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + 9 * UCELLS + TY * kTileX);
+    //
+    // The u ring's row stride is padded to a multiple of the 32 LDS banks where that costs
+    // neither the 32-bit bit words nor a block per CU: the compose's corner reads take rows
+    // and planes that differ from lane to lane, and with the padded stride those rows and
+    // planes fall into the same banks for the same column instead of colliding with the
+    // neighbouring lanes' columns.  (At 16 rows and radius 2 or 3 the padding takes the room
+    // of K~'s ring; measured at radius 3, the padded ring without it is the faster.)
     constexpr int kLdsMax = 160 * 1024, kKrBytes = 12 * WCELLS;
+    constexpr int kLdsRest = 4 * (4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + TY * kTileX) + 4 * 2 * kMaxStructs + 8;
+    constexpr int UWP = (UW + 31) / 32 * 32;
+    constexpr bool kWordsU = TY == 16 && kLdsRest + 36 * UH * UW + 16 * WCELLS <= kLdsMax;
+    constexpr bool kWordsP = TY == 16 && kLdsRest + 36 * UH * UWP + 16 * WCELLS <= kLdsMax;
+    constexpr int kBlocksU = cmin(2048 / NT, kLdsMax / (kLdsRest + 36 * UH * UW + (kMasked ? (kWordsU ? 16 : 4) * WCELLS : 0)));
+    constexpr int kBlocksP = cmin(2048 / NT, kLdsMax / (kLdsRest + 36 * UH * UWP + (kMasked ? (kWordsP ? 16 : 4) * WCELLS : 0)));
+    constexpr int US = kWordsP == kWordsU && kBlocksP >= kBlocksU ? UWP : UW;  // u ring row stride
+    constexpr int UPLANE = US * UH;                                               // and plane stride
+    constexpr int kLdsBase = 4 * (4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + 9 * UPLANE + TY * kTileX);
     // (the 16-row tiles run one block per compute unit; smaller tiles keep bytes so that two
     // blocks fit in its 160 KiB)
     constexpr bool kFr32 = TY == 16 && kLdsBase + 16 * WCELLS <= kLdsMax;
@@ -594,7 +610,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     // One LDS buffer laid out by hand, in order of access density: the arrays read at many
     // constant offsets from one address come first, below 64 KiB, where those offsets fit the
     // LDS instructions' own offset field instead of costing an address add each.
-    constexpr int kRawB = 4 * 3 * HT * WD, kXsB = 4 * 3 * HT * kTileX, kUsB = 4 * 9 * UCELLS;
+    constexpr int kRawB = 4 * 3 * HT * WD, kXsB = 4 * 3 * HT * kTileX, kUsB = 4 * 9 * UPLANE;
     constexpr int kWrB = 4 * 4 * WCELLS, kFrB = kMasked ? 4 * WCELLS * (int)sizeof(FrT) : 4;
     constexpr int kKrB = kStageK ? 4 * 3 * WCELLS : 4, kDqB = 4 * TY * kTileX, kLamB = 4 * 2 * kMaxStructs;
     constexpr int oXs = kRawB, oUs = oXs + kXsB, oWr = oUs + kUsB, oFr = oWr + kWrB;
@@ -603,7 +619,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     __shared__ __attribute__((aligned(16))) char smem[kLdsTotal];
     auto raw = reinterpret_cast<float(*)[HT][WD]>(smem);            // du on the tile + R halo
     auto xs = reinterpret_cast<float(*)[HT][kTileX]>(smem + oXs);
-    auto Us = reinterpret_cast<float(*)[3][UCELLS]>(smem + oUs);    // u planes z-1..z+1,
+    auto Us = reinterpret_cast<float(*)[3][UPLANE]>(smem + oUs);    // u planes z-1..z+1,
                                                                     // slot (p - z0 + 1) % 3
     auto Wr = reinterpret_cast<float(*)[WCELLS]>(smem + oWr);       // I0~ planes, slot = plane & 3
     auto Fr = reinterpret_cast<FrT(*)[WCELLS]>(smem + oFr);         // their stencil structure bits
@@ -726,12 +742,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     };
 
     // ---- u ring (tile + 1 halo) for the compose gathers
-    int uoff[NU];
+    int uoff[NU], uadr[NU];  // global offset and ring cell of each staged u cell
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
         const int c = tid + j * NT;
         const int r = c / UW, q = c - r * UW;
         uoff[j] = clampi(x0 - 1 + q, 0, nx - 1) + nx * clampi(y0 - 1 + r, 0, ny - 1);
+        uadr[j] = r * US + q;
     }
     float upre[NU][3];
     auto u_load = [&](int p) {
@@ -750,9 +767,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
         for (int j = 0; j < NU; ++j) {
             const int c = tid + j * NT;
             if (c < UCELLS) {
-                Us[0][sl][c] = upre[j][0];
-                Us[1][sl][c] = upre[j][1];
-                Us[2][sl][c] = upre[j][2];
+                Us[0][sl][uadr[j]] = upre[j][0];
+                Us[1][sl][uadr[j]] = upre[j][1];
+                Us[2][sl][uadr[j]] = upre[j][2];
             }
         }
     };
@@ -795,7 +812,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < nx && gy < ny;
     const int ntx = (nx + kTileX - 1) / kTileX;
-    const int cbase = (ty + 1) * UW + tx + 1;  // this voxel's cell in a u ring plane
+    const int cbase = (ty + 1) * US + tx + 1;  // this voxel's cell in a u ring plane
     float last[3] = {0.f, 0.f, 0.f};
     int prev = -1;
     if (kMasked && tid < kMaxStructs) {  // (the weights past k are zero; adding a zero is exact)
@@ -929,9 +946,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                               __builtin_fabsf(fz + 0.5f) <= 0.5f;  // (NaN: not near)
             if (near) {
                 // ring cells: the plane's slot base (uniform), then the row and column offset
-                const int zs_m = ((z - z0) % 3) * UCELLS, zs_0 = ((z - z0 + 1) % 3) * UCELLS;
-                const int zs_p = ((z - z0 + 2) % 3) * UCELLS;
-                const int cell = cbase + (int)__builtin_fmaf(fy, (float)UW, fx);
+                const int zs_m = ((z - z0) % 3) * UPLANE, zs_0 = ((z - z0 + 1) % 3) * UPLANE;
+                const int zs_p = ((z - z0 + 2) % 3) * UPLANE;
+                const int cell = cbase + (int)__builtin_fmaf(fy, (float)US, fx);
                 const int i0 = (fz < 0.f ? zs_m : zs_0) + cell, i1 = (fz < 0.f ? zs_0 : zs_p) + cell;
                 const float tx_ = s[0] - fx, ty_ = s[1] - fy, tz_ = s[2] - fz;
 #pragma unroll
@@ -940,12 +957,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                     float f[8];
                     f[0] = U[i0];
                     f[1] = U[i0 + 1];
-                    f[2] = U[i0 + UW];
-                    f[3] = U[i0 + UW + 1];
+                    f[2] = U[i0 + US];
+                    f[3] = U[i0 + US + 1];
                     f[4] = U[i1];
                     f[5] = U[i1 + 1];
-                    f[6] = U[i1 + UW];
-                    f[7] = U[i1 + UW + 1];
+                    f[6] = U[i1 + US];
+                    f[7] = U[i1 + US + 1];
                     stg(a.uc[k], v, s[k] + lerp8(f, tx_, ty_, tz_));
                 }
             } else {

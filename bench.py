@@ -384,10 +384,12 @@ def warm_start(cgdir, torch, pair, pool, iters=30):
     return out
 
 
-def batched(cgdir, torch, pairs):
+def batched(cgdir, torch, pairs, repeats=3):
     """The uneven batch (sizes and structure counts drawn per pair): all pairs in one
     cgdir_register_batch call vs the same pairs registered one at a time, both timed after a
-    pass of each that lets the autotuner settle every tile-shape group they use."""
+    pass of each that lets the autotuner settle every tile-shape group they use, then timed
+    `repeats` times in alternation; the medians are reported (one timing of the batch varies by
+    a few per cent from the next)."""
     dev = torch.device("cuda")
     items = [(torch.from_numpy(p.target).to(dev), torch.from_numpy(p.moving).to(dev),
               torch.from_numpy(p.target_masks).to(dev), torch.from_numpy(p.moving_masks).to(dev))
@@ -401,22 +403,27 @@ def batched(cgdir, torch, pairs):
             ctx.register(*it, pr, o)
         ctx.register_batch(items, prms, outs)           # and of every batched launch group
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for it, pr, o in zip(items, prms, outs):
-            ctx.register(*it, pr, o)
-        torch.cuda.synchronize()
-        serial = time.perf_counter() - t0
-        time.sleep(0.05)   # an idle gap that marks the timed batched run in a kernel trace
-        t0 = time.perf_counter()
-        rc, st = ctx.register_batch(items, prms, outs)
-        torch.cuda.synchronize()
-        batch = time.perf_counter() - t0
-        if rc != cgdir.OK:
-            raise RuntimeError("batch failed: %s" % cgdir.strerror(rc))
-    return {"pairs": len(pairs), "voxel_iterations": vi,
+        serials, batches = [], []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            for it, pr, o in zip(items, prms, outs):
+                ctx.register(*it, pr, o)
+            torch.cuda.synchronize()
+            serials.append(time.perf_counter() - t0)
+            time.sleep(0.05)   # an idle gap that marks each timed batched run in a kernel trace
+            t0 = time.perf_counter()
+            rc, st = ctx.register_batch(items, prms, outs)
+            torch.cuda.synchronize()
+            batches.append(time.perf_counter() - t0)
+            if rc != cgdir.OK:
+                raise RuntimeError("batch failed: %s" % cgdir.strerror(rc))
+    serial, batch = float(np.median(serials)), float(np.median(batches))
+    return {"pairs": len(pairs), "voxel_iterations": vi, "repeats": repeats,
             "batched_value": vi / batch, "batched_ms": batch * 1e3,
             "one_at_a_time_value": vi / serial, "one_at_a_time_ms": serial * 1e3,
             "speedup": serial / batch, "unit": "voxel-iter/s",
+            "batched_ms_each": [round(t * 1e3, 1) for t in batches],
+            "one_at_a_time_ms_each": [round(t * 1e3, 1) for t in serials],
             "sizes": [list(p.dims) for p in pairs], "structures": [p.k for p in pairs]}
 
 

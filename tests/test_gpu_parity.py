@@ -302,6 +302,25 @@ def test_full_run_pyramid_contour_terms_at_every_level(ctx, orc):
     assert err <= FINAL_TOL and rms <= WARP_RMS_TOL
 
 
+def test_full_run_pyramid_anisotropic_in_plane_with_contour_terms_at_every_level(ctx, orc):
+    """Three levels in physical units with x, y and z voxel sizes that all differ (1.1 x 1.6 x
+    2.2 mm, sigma 2 mm: radii 6, 4, 3 at the finest level) and contour terms at each level,
+    20 iterations per level: every launch takes the kernels' general instantiation."""
+    from paper_1301_0970_amd import cgdir
+    pair = P.pelvis_pair(dims=(90, 70, 36), amp=4.0, k=3, levels=3, iters=20, bulge=2.0, seed=91)
+    h = (1.1, 1.6, 2.2)
+    say("full run pyramid 90x70x36 3x20 in %s mm, contour terms at every level" % (h,))
+    ug = gpu_register(ctx, pair, cgdir.params_for_pair(pair, sigma_fluid=2.0, sigma_diff=2.0, spacing=h,
+                                                       contour_level_mask=7))
+    uo, _, _ = orc.register(pair.target, pair.moving, pair.target_masks, pair.moving_masks,
+                            orc.params_for(pair, sigma_fluid=2.0, sigma_diff=2.0, contour_level_mask=7,
+                                           spacing=[float(np.float32(v)) for v in h]))
+    err = np.abs(ug - uo).max()
+    rms = np.sqrt(((orc.warp(pair.moving, ug) - orc.warp(pair.moving, uo)) ** 2).mean())
+    say("  final max err %.3g voxel, warped rms %.3g HU" % (err, rms))
+    assert err <= FINAL_TOL and rms <= WARP_RMS_TOL
+
+
 def test_identity_stays_zero(ctx):
     """P4 on the GPU: identical images and masks give exactly u = 0."""
     from paper_1301_0970_amd import cgdir

@@ -20,6 +20,12 @@
  *  - UROI: union of the target structures dilated by an ellipsoid (5, 5, 4) voxels;
  *  - stopping: after every `window` finest-level iterations, stop when
  *    delta_{n-window} - delta_n <= eps (n = the last iteration run).
+ *
+ * Parity unpinned: no number in the paper tests these readings, so the pins check each
+ * function against its definition and library routines but not the choice itself: c0, the
+ * restriction's sigma = 1 filter, the UROI's ellipsoid, the form of the stopping rule, the
+ * clamped borders of the gradient, the interpolation and the Gaussian, the per-level voxel
+ * size spacing * 2^l, and the coarse-level masks taken at the voxels the restriction keeps.
  */
 #include "cgdir_oracle.h"
 

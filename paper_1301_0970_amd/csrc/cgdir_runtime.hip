@@ -241,8 +241,10 @@ class Tuner {
     }
 
     // shape to use for the next launch of group `key`; *measure >= 0 asks the caller to time
-    // the launch with events ev[0], ev[1] and hand them back through record()
-    TileCfg choose(bool step, const std::string &key, int *measure)
+    // the launch with events ev[0], ev[1] and hand them back through record().  Candidates for
+    // which too_fine() holds are not tried (nor chosen).
+    template <class TooFine>
+    TileCfg choose(bool step, const std::string &key, int *measure, TooFine &&too_fine)
     {
         *measure = -1;
         const TileCfg *c = step ? kStepCands : kSmoothCands;
@@ -251,6 +253,8 @@ class Tuner {
         Entry &e = table_[key];
         if (e.ms.empty()) e.ms.assign(nc, {});
         if (settle_if_measured(key, e)) return c[e.best];
+        while (e.next < nc && too_fine(c[e.next])) ++e.next;  // (left untimed: never a finalist
+                                                               // while three others are timed)
         if (e.next < nc) {  // first round: every candidate once
             *measure = e.next;
             return c[e.next++];
@@ -1192,12 +1196,20 @@ int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::v
     // a launch, timed for the tuner when it asks
     // settled_only: tile shapes the tuner has settled (else its first candidate), no timing
     // events and no profiling events (cgdir_register_static creates no HIP objects)
-    auto pick = [&](bool step, const std::string &key, int *cand) {
+    // z chunks of fewer than 8 planes recompute their 2R halo planes for few outputs; they pay
+    // only where 8-plane chunks leave the device short of blocks (fewer than 4 per CU), so the
+    // tuner does not try them elsewhere
+    auto pick = [&](bool step, const std::string &key, int *cand, const std::vector<Dims> &dims) {
         if (settled_only) {
             *cand = -1;
             return c->tuner.settled_or_default(step, key);
         }
-        return c->tuner.choose(step, key, cand);
+        return c->tuner.choose(step, key, cand, [&](const TileCfg &t) {
+            if (t.tz >= 8) return false;
+            int64_t blocks = 0;
+            for (const Dims &d : dims) blocks += tile_blocks(d, t.ty, 8);
+            return blocks >= 1024;
+        });
     };
     auto tuned = [&](bool measure_it, const std::string &key, int cand, double voxels, auto &&fn) -> hipError_t {
         if (!measure_it) return fn();
@@ -1222,8 +1234,10 @@ int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::v
             StepBatch sb{};
             sb.n = (int)std::min<size_t>(kBatchStep, v.size() - b);
             const std::string key = shapes_key('U', g.first, &v[b], sb.n);
+            std::vector<Dims> dims;
+            for (int q = 0; q < sb.n; ++q) dims.push_back(level_dims(jobs[v[b + q]]->d0, jobs[v[b + q]]->level));
             int cand = -1;
-            const TileCfg cfg = pick(true, key, &cand);
+            const TileCfg cfg = pick(true, key, &cand, dims);
             double vox = 0.0;
             for (int q = 0; q < sb.n; ++q) {
                 sb.d[q] = jobs[v[b + q]]->step_args();
@@ -1256,8 +1270,10 @@ int run_tick(cgdir_ctx *c, hipStream_t s, const std::vector<Job *> &jobs, std::v
             SmoothBatch sb{};
             sb.n = (int)std::min<size_t>(kBatchSmooth, v.size() - b);
             const std::string key = shapes_key('S', g.first, &v[b], sb.n);
+            std::vector<Dims> dims;
+            for (int q = 0; q < sb.n; ++q) dims.push_back(level_dims(jobs[v[b + q]]->d0, jobs[v[b + q]]->level));
             int cand = -1;
-            const TileCfg cfg = pick(false, key, &cand);
+            const TileCfg cfg = pick(false, key, &cand, dims);
             double vox = 0.0;
             for (int q = 0; q < sb.n; ++q) {
                 sb.d[q] = jobs[v[b + q]]->smooth_args();

@@ -67,9 +67,17 @@ def test_batch_rejects_when_pool_too_small():
         assert rc == cgdir.E_NOMEM
 
 
-def test_served_equals_alone_and_reports_latency():
+@pytest.mark.parametrize("policy,large", [("2", None), ("2", "200000"), ("1", "200000"), ("0", "200000")],
+                         ids=["default", "lanes one at a time", "lanes", "lockstep"])
+def test_served_equals_alone_and_reports_latency(policy, large, monkeypatch):
+    """Served fields equal each pair alone under every serving policy; with the large-request
+    threshold below three of the four pair sizes (CGDIR_SERVE_LARGE, read when the context is
+    created) requests change lanes as others join and leave."""
     import torch
     from paper_1301_0970_amd import cgdir
+    monkeypatch.setenv("CGDIR_SERVE_POLICY", policy)
+    if large is not None:
+        monkeypatch.setenv("CGDIR_SERVE_LARGE", large)
     pairs = _pairs(scale=10) * 2
     items = _items(pairs)
     prms = [cgdir.params_for_pair(p) for p in pairs]

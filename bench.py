@@ -405,12 +405,13 @@ def batched(cgdir, torch, pairs, repeats=3):
         torch.cuda.synchronize()
         serials, batches = [], []
         for _ in range(repeats):
+            time.sleep(0.05)   # idle gaps that mark each timed run (serial, then batched) in a trace
             t0 = time.perf_counter()
             for it, pr, o in zip(items, prms, outs):
                 ctx.register(*it, pr, o)
             torch.cuda.synchronize()
             serials.append(time.perf_counter() - t0)
-            time.sleep(0.05)   # an idle gap that marks each timed batched run in a kernel trace
+            time.sleep(0.05)
             t0 = time.perf_counter()
             rc, st = ctx.register_batch(items, prms, outs)
             torch.cuda.synchronize()
@@ -530,6 +531,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, metavar="PAIRS",
                     help="pairs of the uneven batched workload (0: skip it)")
+    ap.add_argument("--batch-repeats", type=int, default=3,
+                    help="timed repeats of the batched and the one-at-a-time runs (medians reported)")
     ap.add_argument("--serve-seconds", type=float, default=120.0,
                     help="duration of the served workload's arrivals (0: skip serving)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals per second")
@@ -652,7 +655,7 @@ def main():
         result["evaluation"] = evaluated(cgdir, torch, pair, pool + (1 << 30))
     if batch_pairs:
         log("batched workload")
-        result["batched"] = batched(cgdir, torch, batch_pairs)
+        result["batched"] = batched(cgdir, torch, batch_pairs, args.batch_repeats)
     if serve_pairs:
         log("served workload")
         result["served"] = serving(cgdir, P, torch, serve_pairs, args.serve_rate, args.serve_seconds,

@@ -10,6 +10,7 @@ namespace cgdir {
 constexpr int kMaxStructs = 8;
 constexpr int kMaxRadius = 6;       // Gaussian radius ceil(3 sigma) <= 6  (sigma <= 2)
 constexpr int kTileX = 64;          // one wavefront spans a tile row
+constexpr int kComputeUnits = 256;  // of an MI355X (8 XCDs x 32)
 constexpr int kMaxUroiMargin = 8;
 
 // Geometry of one volume.

@@ -476,8 +476,16 @@ __device__ __forceinline__ void smooth_tile(const SmoothArgs &a, int L)
     WarpPending wp;
     int wv = -1;
     const int lo = z0 - R, count = (z1 - z0) + 2 * R;  // planes lo .. lo + count - 1
+    // Two blocks share a compute unit.  The SIMDs issue from the older block's waves first, so
+    // left alone it finishes well before the younger one (measured on full launches: the
+    // first-dispatched blocks end about 60 us of 400 earlier) and the unit then runs half its
+    // waves.  The blocks of even and odd passes of the dispatcher over the 256 units take the
+    // higher issue priority on alternate steps instead, so that both advance at one pace.
+    const int pass = (blockIdx.x / kComputeUnits) & 1;
     prefetch(lo);
     for (int i = 0; i < count + 2; ++i) {
+        if ((i + pass) & 1) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
         // (a) plane lo + i into raw[i & 1], and the next plane's prefetch
         if (i < count) {
             const int sb = i & 1;

@@ -105,7 +105,11 @@ def generate(specs, workers):
     """The pairs of a list of specs, drawn in parallel worker processes (numpy only; started
     before this process touches the GPU)."""
     if workers <= 1 or len(specs) <= 1:
-        return [_pair_from_spec(s) for s in specs]
+        out = []
+        for i, s in enumerate(specs):
+            out.append(_pair_from_spec(s))
+            log("  pair %d of %d" % (i + 1, len(specs)))
+        return out
     import multiprocessing as mp
     with mp.get_context("spawn").Pool(min(workers, len(specs))) as pool:
         return pool.map(_pair_from_spec, specs, chunksize=1)
@@ -546,6 +550,9 @@ def main():
                     help="also time the first registration of a fresh context, untuned and with imported tile shapes")
     ap.add_argument("--evaluate", action="store_true",
                     help="also evaluate (section 2.3 metrics) CG-DIR, CG-DIR with contour terms at every level and plain demons on the workload")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="worker processes that draw the batched and served pairs (1: in this process, "
+                         "e.g. under a profiler that would also load itself into every worker)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -573,7 +580,7 @@ def main():
     desc, make = WORKLOADS[args.workload]
     log("generating %s" % args.workload)
     pair = make(P)
-    workers = min(16, len(os.sched_getaffinity(0)))
+    workers = max(1, min(args.gen_workers, len(os.sched_getaffinity(0))))
     batch_pairs, serve_pairs = [], []
     if args.batch:
         log("generating the uneven batch (%d pairs)" % args.batch)

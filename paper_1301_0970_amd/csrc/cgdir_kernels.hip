@@ -592,51 +592,63 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
     // for the 16-row tiles (one block per CU: the slowest block sets the launch's time) K~
     // of three staged planes (the warped masked moving image of the one structure near a
     // cell), so that the force near a structure reads no memory.  (Smaller tiles keep their
-    // LDS small so that more blocks share a CU.)
+    // LDS small so that more blocks share a CU.)  The I0~ and bit rings of the 16-row tiles
+    // hold three planes (four for smaller tiles): a plane's slot is refilled once every wave
+    // has passed the force of the plane above it.
     //
     // The u ring's row stride is padded to a multiple of the 32 LDS banks where that costs
     // neither the 32-bit bit words nor a block per CU: the compose's corner reads take rows
     // and planes that differ from lane to lane, and with the padded stride those rows and
     // planes fall into the same banks for the same column instead of colliding with the
-    // neighbouring lanes' columns.  (At 16 rows and radius 2 or 3 the padding takes the room
-    // of K~'s ring; measured at radius 3, the padded ring without it is the faster.)
-    constexpr int kLdsMax = 160 * 1024, kKrBytes = 12 * WCELLS;
-    constexpr int kLdsRest = 4 * (4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + TY * kTileX) + 4 * 2 * kMaxStructs + 8;
-    constexpr int UWP = (UW + 31) / 32 * 32;
-    constexpr bool kWordsU = TY == 16 && kLdsRest + 36 * UH * UW + 16 * WCELLS <= kLdsMax;
-    constexpr bool kWordsP = TY == 16 && kLdsRest + 36 * UH * UWP + 16 * WCELLS <= kLdsMax;
-    constexpr int kBlocksU = cmin(2048 / NT, kLdsMax / (kLdsRest + 36 * UH * UW + (kMasked ? (kWordsU ? 16 : 4) * WCELLS : 0)));
-    constexpr int kBlocksP = cmin(2048 / NT, kLdsMax / (kLdsRest + 36 * UH * UWP + (kMasked ? (kWordsP ? 16 : 4) * WCELLS : 0)));
-    constexpr int US = kWordsP == kWordsU && kBlocksP >= kBlocksU ? UWP : UW;  // u ring row stride
-    constexpr int UPLANE = US * UH;                                               // and plane stride
-    constexpr int kLdsBase = 4 * (4 * WCELLS + 3 * HT * WD + 3 * HT * kTileX + 9 * UPLANE + TY * kTileX);
-    // (the 16-row tiles run one block per compute unit; smaller tiles keep bytes so that two
-    // blocks fit in its 160 KiB)
-    constexpr bool kFr32 = TY == 16 && kLdsBase + 16 * WCELLS <= kLdsMax;
-    constexpr bool kStageK = kMasked && TY == 16 && kLdsBase + 16 * WCELLS + kKrBytes <= kLdsMax;
+    // neighbouring lanes' columns.  The padding columns then hold the squared metric terms
+    // and the weight table.
+    constexpr int kLdsMax = 160 * 1024, kSlots = TY == 16 ? 3 : 4;
+    constexpr int UWP = (UW + 31) / 32 * 32, PADW = UWP - UW;
+    static_assert(PADW > 0, "the u ring rows are padded to a multiple of 32");
+    constexpr int kDqF = TY * kTileX, kLamF = 2 * kMaxStructs;  // floats of the metric terms, weights
+    // (whole rows of padding for the metric terms, the last row's for the weights; only for
+    // the 16-row tiles, where the 160 KiB are short)
+    constexpr bool kSideFits = TY == 16 && PADW >= kLamF && (kDqF + PADW - 1) / PADW <= 9 * UH - 1;
+    constexpr int kFixedB = 4 * (kSlots * WCELLS + 3 * HT * WD + 3 * HT * kTileX);  // I0~, du, x pass
+    constexpr int kLdsU = kFixedB + 36 * UH * UW + 4 * (kDqF + kLamF);
+    constexpr int kLdsP = kFixedB + 36 * UH * UWP + (kSideFits ? 0 : 4 * (kDqF + kLamF));
+    constexpr int kFrWordsB = 4 * kSlots * WCELLS, kFrBytesB = kSlots * WCELLS;
+    constexpr bool kWordsU = TY == 16 && kLdsU + kFrWordsB <= kLdsMax;
+    constexpr bool kWordsP = TY == 16 && kLdsP + kFrWordsB <= kLdsMax;
+    constexpr int kBlocksU = cmin(2048 / NT, kLdsMax / (kLdsU + (kMasked ? (kWordsU ? kFrWordsB : kFrBytesB) : 0)));
+    constexpr int kBlocksP = cmin(2048 / NT, kLdsMax / (kLdsP + (kMasked ? (kWordsP ? kFrWordsB : kFrBytesB) : 0)));
+    constexpr bool kPad = kWordsP == kWordsU && kBlocksP >= kBlocksU;
+    constexpr bool kSideInPad = kPad && kSideFits;
+    constexpr int US = kPad ? UWP : UW;  // u ring row stride
+    constexpr int UPLANE = US * UH;      // and plane stride
+    constexpr int kLdsBase = kPad ? kLdsP : kLdsU;
+    constexpr bool kFr32 = TY == 16 && kLdsBase + kFrWordsB <= kLdsMax;
+    constexpr bool kStageK = kMasked && TY == 16 && kLdsBase + kFrWordsB + 12 * WCELLS <= kLdsMax;
     using FrT = typename std::conditional<kFr32, uint32_t, uint8_t>::type;
     // One LDS buffer laid out by hand, in order of access density: the arrays read at many
     // constant offsets from one address come first, below 64 KiB, where those offsets fit the
     // LDS instructions' own offset field instead of costing an address add each.
     constexpr int kRawB = 4 * 3 * HT * WD, kXsB = 4 * 3 * HT * kTileX, kUsB = 4 * 9 * UPLANE;
-    constexpr int kWrB = 4 * 4 * WCELLS, kFrB = kMasked ? 4 * WCELLS * (int)sizeof(FrT) : 4;
-    constexpr int kKrB = kStageK ? 4 * 3 * WCELLS : 4, kDqB = 4 * TY * kTileX, kLamB = 4 * 2 * kMaxStructs;
+    constexpr int kWrB = 4 * kSlots * WCELLS, kFrB = kMasked ? kSlots * WCELLS * (int)sizeof(FrT) : 4;
+    constexpr int kKrB = kStageK ? 4 * 3 * WCELLS : 4, kSideB = kSideInPad ? 4 : 4 * (kDqF + kLamF);
     constexpr int oXs = kRawB, oUs = oXs + kXsB, oWr = oUs + kUsB, oFr = oWr + kWrB;
-    constexpr int oKr = oFr + ((kFrB + 3) & ~3), oDq = oKr + kKrB, oLam = oDq + kDqB, kLdsTotal = oLam + kLamB;
+    constexpr int oKr = oFr + ((kFrB + 3) & ~3), oSide = oKr + kKrB, kLdsTotal = oSide + kSideB;
     static_assert(kLdsTotal <= kLdsMax, "LDS budget of the step kernel");
     __shared__ __attribute__((aligned(16))) char smem[kLdsTotal];
     auto raw = reinterpret_cast<float(*)[HT][WD]>(smem);            // du on the tile + R halo
     auto xs = reinterpret_cast<float(*)[HT][kTileX]>(smem + oXs);
     auto Us = reinterpret_cast<float(*)[3][UPLANE]>(smem + oUs);    // u planes z-1..z+1,
                                                                     // slot (p - z0 + 1) % 3
-    auto Wr = reinterpret_cast<float(*)[WCELLS]>(smem + oWr);       // I0~ planes, slot = plane & 3
+    auto Wr = reinterpret_cast<float(*)[WCELLS]>(smem + oWr);       // I0~ planes, slot = plane % 3
     auto Fr = reinterpret_cast<FrT(*)[WCELLS]>(smem + oFr);         // their stencil structure bits
     auto Kr = reinterpret_cast<float(*)[WCELLS]>(smem + oKr);       // K~ where the bits are
                                                                     // nonzero, slot = plane % 3
-    auto dq = reinterpret_cast<float(*)[kTileX]>(smem + oDq);       // squared metric terms of the
-                                                                    // tile's voxels
-    auto lamt = reinterpret_cast<float(*)[kMaxStructs]>(smem + oLam);  // lambda_i; the sum of the
-                                                                       // other weights
+    // the squared metric terms of the tile's voxels, voxel d = row * 64 + column at dq[dq_at(d)],
+    // and lambda_i with the sum of the other weights in index order (16 floats)
+    float *const dq = reinterpret_cast<float *>(smem + (kSideInPad ? oUs : oSide));
+    auto dq_at = [](int d) { return kSideInPad ? (d / PADW) * US + UW + d % PADW : d; };
+    float *const lamt = kSideInPad ? reinterpret_cast<float *>(smem + oUs) + (9 * UH - 1) * US + UW
+                                   : reinterpret_cast<float *>(smem + oSide) + kDqF;
 
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
@@ -674,15 +686,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                 pf[j] = masked ? ldg(a.F, base + woff[j]) : 0u;
             }
     };
-    // w_store also issues the K~ loads of the cells whose bits are nonzero; k_store puts them
-    // into the K~ ring once the plane they replace is no longer read (after the next force
-    // pass) and their latency is covered
-    float pk[NW];
-    uint32_t kpend = 0u;
-    int kplane = 0;
-    bool kwave = false;  // this wave has K~ loads pending
-    auto w_store = [&](int p) {
-        const int sl = p & 3;
+    // w_put stores a loaded plane into its ring slot (once no wave reads the plane it replaces);
+    // k_issue issues the K~ loads of the cells whose bits are nonzero, and k_store puts them
+    // into the K~ ring once the plane they replace is no longer read and their latency is covered
+    auto w_put = [&](int p) {
+        const int sl = p % kSlots;
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
             const int c = tid + j * NT;
@@ -691,6 +699,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                 if constexpr (kMasked) Fr[sl][c] = (FrT)pf[j];
             }
         }
+    };
+    float pk[NW];
+    uint32_t kpend = 0u;
+    int kplane = 0;
+    bool kwave = false;  // this wave has K~ loads pending
+    auto k_issue = [&](int p) {
         if constexpr (kStageK) {
             kpend = 0u;
             kplane = p;
@@ -733,7 +747,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
         cgx[j] = clampi(x0 - R + q, 0, nx - 1);
         cgy[j] = clampi(y0 - R + r, 0, ny - 1);
         const bool tile = c < CELLS && r >= R && r < R + TY && q >= R && q < R + kTileX;
-        dqi[j] = tile ? (r - R) * kTileX + (q - R) : -1;
+        dqi[j] = tile ? dq_at((r - R) * kTileX + (q - R)) : -1;
         if (tile && x0 + q - R < nx && y0 + r - R < ny) inside |= 1u << j;
     }
     float pt[NP];
@@ -796,18 +810,21 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
         }
     };
 
-    // planes pa - 1 .. pa + 1 staged, pa + 2 in registers; plane q + 2 is staged while
-    // plane q's du is evaluated, into the slot of plane q - 2
+    // planes pa - 1 .. pa + 1 staged, pa + 2 in registers; plane q + 2 is staged once every
+    // wave has evaluated plane q's du, into the slot of plane q - 1
     const int zs = z0 - R, ze = z1 - 1 + R;
     const int pa = max(zs, 0), pb = min(ze, nz - 1);
     w_load(max(pa - 1, 0));
-    w_store(max(pa - 1, 0));
+    w_put(max(pa - 1, 0));
+    k_issue(max(pa - 1, 0));
     k_store();
     w_load(pa);
-    w_store(pa);
+    w_put(pa);
+    k_issue(pa);
     k_store();
     w_load(min(pa + 1, nz - 1));
-    w_store(min(pa + 1, nz - 1));
+    w_put(min(pa + 1, nz - 1));
+    k_issue(min(pa + 1, nz - 1));
     k_store();
     w_load(min(pa + 2, nz - 1));
     t_load(pa);
@@ -831,8 +848,8 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             li = m == tid ? lm : li;
             off += m == tid ? 0.f : lm;
         }
-        lamt[0][tid] = li;
-        lamt[1][tid] = off;
+        lamt[tid] = li;
+        lamt[kMaxStructs + tid] = off;
     }
     __syncthreads();
     for (int l = zs; l <= ze; ++l) {
@@ -842,7 +859,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
         float v3[3];
         if (pc != prev) {
             // ---- du on plane pc, tile + R halo
-            const int s0 = pc & 3, sm = max(pc - 1, 0) & 3, sp = min(pc + 1, nz - 1) & 3;
+            const int s0 = pc % kSlots, sm = max(pc - 1, 0) % kSlots, sp = min(pc + 1, nz - 1) % kSlots;
             // K~ ring slots of this plane and the ones below and above (slot = plane % 3)
             const int kslots[3] = {(pc % 3) * WCELLS, (max(pc - 1, 0) % 3) * WCELLS,
                                    (min(pc + 1, nz - 1) % 3) * WCELLS};
@@ -874,23 +891,27 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
                         for (int q = 0; q < 7; ++q) f7[q] = 0u;
                     }
                     float du[3], d;
-                    force_at<kStageK, WW, kAniso>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, &lamt[0][0],
+                    force_at<kStageK, WW, kAniso>(a, w7, f7, pt[j], ptb[j], cx, cy, pc, lamt,
                                           kStageK ? &Kr[0][0] + wo : nullptr, kslots, du, &d);
                     (&raw[0][0][0])[c] = du[0];  // cell c is row c / WD, column c % WD
                     (&raw[1][0][0])[c] = du[1];
                     (&raw[2][0][0])[c] = du[2];
                     if (metric && dqi[j] >= 0) {
                         const float e = d * a.inv_norm;
-                        (&dq[0][0])[dqi[j]] = pur[j] ? e * e : 0.f;
+                        dq[dqi[j]] = pur[j] ? e * e : 0.f;
                     }
                 }
             }
-            // the loads are clamped into the volume and issued unconditionally (a few
-            // unused planes at the chunk end) so that no register copies are needed
-            if (pc + 1 <= pb && pc + 2 <= nz - 1) w_store(pc + 2);
+            // plane pc + 2 into the slot of plane pc - 1 once every wave is past this plane's
+            // force (its K~ loads issued before the barrier); the loads are clamped into the
+            // volume and issued unconditionally (a few unused planes at the chunk end) so that
+            // no register copies are needed
+            const bool stage = pc + 1 <= pb && pc + 2 <= nz - 1;
+            if (stage) k_issue(pc + 2);
+            __syncthreads();
+            if (stage) w_put(pc + 2);
             w_load(min(pc + 3, nz - 1));
             t_load(min(pc + 1, nz - 1));
-            __syncthreads();
             for (int c = tid; c < HT * kTileX; c += NT) {
                 const int r = c / kTileX, q = c - r * kTileX;
 #pragma unroll
@@ -905,7 +926,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int L)
             // stopping metric: one partial per 64-voxel row segment (a wave is one tile
             // row), a grouping that does not depend on the launch geometry
             if (metric && pc >= z0 && pc < z1 && gy < ny) {
-                const float rs = wave_sum(dq[ty][tx]);
+                const float rs = wave_sum(dq[dq_at(ty * kTileX + tx)]);
                 if (tx == 0) stg(a.partials, (pc * ny + gy) * ntx + x0 / kTileX, rs);
             }
             if (out) {

@@ -94,12 +94,13 @@ def test_teacher_forced_step(ctx, orc, name, kw, k, sigma, famp):
     assert err <= STEP_TOL
 
 
-def test_structures_at_every_border_under_every_tile_shape(ctx, orc):
+@pytest.mark.parametrize("sigma", [1.0, 0.6], ids=["radius 3", "radius 2"])
+def test_structures_at_every_border_under_every_tile_shape(ctx, orc, sigma):
     """Structures cut by the volume's faces (one around the corner (0, 0, 0), one around the
     opposite corner, one slab through every plane), so that the step kernel stages structure
     bits and K~ at clamped planes, rows and columns: one teacher-forced iteration under every
     tile shape the autotuner tries is bitwise the same field, and within 1e-4 voxel of the
-    FP64 oracle."""
+    FP64 oracle (Gaussian radius 3 and 2, whose 16-row tiles stage K~ in LDS)."""
     from paper_1301_0970_amd import cgdir
     pair = P.plain_pair(dims=(140, 52, 20), amp=3.0)
     nx, ny, nz = pair.dims
@@ -113,13 +114,13 @@ def test_structures_at_every_border_under_every_tile_shape(ctx, orc):
     pair.target_masks, pair.moving_masks, pair.signs = masks(0), masks(1), (1, -1, 1)
     u0 = P.random_smooth_field(pair.dims, 2.5, 303)
     lam, sg = [1e-3, 2e-3, 3e-3], [1, -1, 1]
-    prm = cgdir.make_params(levels=1, iters=(1,), sigma_fluid=1.0, sigma_diff=1.0, lambdas=lam, signs=sg)
-    say("structures at the borders: every tile shape")
+    prm = cgdir.make_params(levels=1, iters=(1,), sigma_fluid=sigma, sigma_diff=sigma, lambdas=lam, signs=sg)
+    say("structures at the borders: every tile shape (sigma %g)" % sigma)
     first = gpu_register(ctx, pair, prm, initial=u0)
     for i in range(18):               # the autotuner's candidate shapes, then the tuned one
         again = gpu_register(ctx, pair, prm, initial=u0)
         assert np.array_equal(first, again), i
-    uo = oracle_step(orc, pair, u0, 1.0, 1.0, lam, sg)
+    uo = oracle_step(orc, pair, u0, sigma, sigma, lam, sg)
     err = np.abs(first - uo).max()
     say("  max |du| %.3g  max err %.3g" % (np.abs(uo - u0).max(), err))
     assert err <= STEP_TOL

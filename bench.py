@@ -163,8 +163,16 @@ def log(msg):
 
 
 def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_1301_0970_amd", "csrc", "cgdir_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (16 hex digits) of the kernel sources with their comments and runs of blank space
+    removed: the counter summaries under profiles/ stay attached to the code they measured when
+    only a comment changes, and are set aside when the code does."""
+    h = hashlib.sha256()
+    for name in ("cgdir_kernels.hip", "cgdir_internal.h"):
+        with open(os.path.join(ROOT, "paper_1301_0970_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", re.sub(r"//[^\n]*", " ", src), flags=re.S)
+        h.update(re.sub(r"\s+", " ", src).strip().encode())
+    return h.hexdigest()[:16]
 
 
 def read_profile(workload, what):

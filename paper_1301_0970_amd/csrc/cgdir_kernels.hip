@@ -574,9 +574,10 @@ __global__ void __launch_bounds__(kTileX *TY) k_smooth_batch(SmoothBatch b)
 // evaluates du on the tile + R halo (the cells the x and y passes read), straight into LDS,
 // so du never goes to memory.  A halo cell is evaluated at its clamped voxel, which gives
 // the clamped-index smoothing exactly.  The I0~ planes (and structure bits) of the stencils,
-// tile + R + 1 halo, go through a 4-slot LDS ring indexed by plane, prefetched one plane
-// ahead; the field's planes around the output plane (tile + 1 halo) go through a 3-slot
-// ring for the compose gathers, with a global fallback when |s| >= 1.
+// tile + R + 1 halo, go through an LDS ring indexed by plane (three slots for 16-row tiles,
+// four for smaller ones), loaded two planes ahead; the field's planes around the output plane
+// (tile + 1 halo) go through a 3-slot ring for the compose gathers, with a global fallback
+// when |s| >= 1.
 // ============================================================================
 // kMasked false: no pair of the launch has contour terms at its level (no structure bits, K~
 // or contour weights in LDS, so the block needs less of it and of registers).

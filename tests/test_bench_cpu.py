@@ -77,3 +77,21 @@ def test_counter_summaries_feed_traffic_valu_and_bound():
     hbm_busy = measured / copy
     assert r["bound"] == ("hbm" if hbm_busy >= r["valu"]["frac"] else "alu")
     assert "waves waiting" in r["bound_evidence"]
+
+
+def test_kernel_source_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    """The counter summaries are matched to the kernel sources by a hash that ignores comments
+    and blank space: editing a comment keeps it, editing code changes it."""
+    src = os.path.join(ROOT, "paper_1301_0970_amd", "csrc")
+    dst = tmp_path / "paper_1301_0970_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for name in ("cgdir_kernels.hip", "cgdir_internal.h"):
+        (dst / name).write_text(open(os.path.join(src, name)).read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    base = bench.kernel_source_hash()
+    k = dst / "cgdir_kernels.hip"
+    text = k.read_text()
+    k.write_text(text.replace("// ", "//  a reworded comment ", 1) + "\n/* a new\n block comment */\n\n")
+    assert bench.kernel_source_hash() == base
+    k.write_text(text.replace("kTileX", "kTileX ", 1).replace("+ 1", "+ 2", 1))
+    assert bench.kernel_source_hash() != base
